@@ -1,0 +1,165 @@
+/*
+ * rp.h -- C-ABI of the MI355X (gfx950) RP-Tuning library.
+ *
+ * Paper: "Prune, Don't Rebuild: Efficiently Tuning alpha-Reachable Graphs for
+ * Nearest Neighbor Search" (arXiv 2602.08097).
+ *
+ * RP-Tuning (Section 3) re-runs RobustPrune (Algorithm 1) on the existing
+ * out-list of every vertex of a base graph at a new alpha (and a degree bound
+ * R), instead of rebuilding the index.  GreedySearch (Algorithm 2) scores the
+ * pruned graphs.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every array argument is a DEVICE pointer owned by the caller, unless the
+ *   argument says "host".  The library never frees caller memory.
+ * - Work is enqueued on the HIP stream passed as `stream` (a hipStream_t; NULL
+ *   is the default stream) and is ordered with the caller's other work on that
+ *   stream.  Calls return once the work is enqueued, except where noted.
+ * - Argument errors are detected on the host and returned before any launch.
+ *   A HIP launch failure returns RP_EDEVICE.  No exception or abort crosses
+ *   the ABI.  rp_last_error() describes the last failure of the calling thread.
+ * - Distances are squared Euclidean (every experiment of Section 4 uses
+ *   Euclidean distance; both sides of every comparison are non-negative, so
+ *   comparing squares is equivalent):
+ *     uint8 points  : exact integers;
+ *     float32 points: the canonical FP64 value
+ *                       acc = 0; for k in 0..d-1:
+ *                         t = (double)a[k] - (double)b[k]; acc = fma(t, t, acc)
+ * - alpha = num/den, num >= den >= 1, both <= 65535.  The pruning condition of
+ *   Algorithm 1, alpha * D(p*, p') <= D(p, p'), is evaluated as
+ *     uint8  : num^2 * S(p*, p') <= den^2 * S(p, p')          (exact integers)
+ *     float32: fl(num^2 * S(p*, p')) <= fl(den^2 * S(p, p'))  (FP64, one rounding
+ *                                                              per product)
+ * - Ties in every argmin, truncation and top-k are broken by (S, id), smallest
+ *   first, so every result is unique and bit-reproducible.
+ * - A graph's adjacency is a fixed-stride n x r_max int32 array: row p holds
+ *   deg[p] ids (0 <= deg[p] <= r_max), the rest of the row is ignored.  A list
+ *   may contain p itself and repeated ids; RobustPrune drops both
+ *   (V <- (V u N_out(p)) \ {p} in Algorithm 1).
+ */
+#ifndef RP_H
+#define RP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rp_graph* rp_graph_t; /* opaque, library-owned */
+
+typedef enum { RP_U8 = 1, RP_F32 = 2 } rp_dtype;
+
+typedef struct {
+  int32_t num;
+  int32_t den;
+} rp_alpha; /* alpha = num / den */
+
+typedef enum {
+  RP_OK = 0,
+  RP_EINVAL = 1,  /* invalid argument (null pointer, bad size, alpha < 1, k > L, ...) */
+  RP_ERANGE = 2,  /* an id or degree in the adjacency is out of range */
+  RP_ENOMEM = 3,  /* device allocation failed */
+  RP_EDEVICE = 4, /* a HIP call or kernel launch failed */
+  RP_ESTATE = 5   /* the graph handle is unusable (e.g. freed base) */
+} rp_status;
+
+/* Device-side counters of a graph handle (see rp_read_counters). */
+typedef struct {
+  int64_t nodes;      /* node-prunes completed (nodes x outputs)             */
+  int64_t pairs;      /* candidate pairs decided by the pruning condition    */
+  int64_t rechecks;   /* pairs re-evaluated in canonical FP64 (float32 data) */
+} rp_counters;
+
+/*
+ * rp_load_graph -- register a point set and its base graph (the input of
+ * RP-Tuning, Section 3).
+ *   points : n x d row-major, uint8 (dtype RP_U8) or float32 (RP_F32).
+ *   n      : 1 <= n < 2^31.   d: 1 <= d <= 4096.
+ *   nbr    : n x r_max int32 out-lists, deg: n int32 out-degrees.
+ *   r_max  : 1 <= r_max <= 256.
+ *   start  : start vertex s of GreedySearch (Algorithm 2), 0 <= start < n.
+ * The library BORROWS points, nbr and deg until rp_free_graph: they must stay
+ * valid and unmodified.  The adjacency is validated on the device; this call
+ * synchronises `stream` and returns RP_ERANGE if any degree is outside
+ * [0, r_max] or any listed id outside [0, n).  On success *out receives a new
+ * handle.
+ */
+rp_status rp_load_graph(const void* points, int32_t dtype, int64_t n, int32_t d,
+                        const int32_t* nbr, const int32_t* deg, int32_t r_max,
+                        int32_t start, void* stream, rp_graph_t* out);
+
+/*
+ * rp_graph_derive -- a handle on another graph over the same points (for
+ * example a pruned graph, to search it).  Shares base's points and start
+ * vertex; borrows nbr/deg like rp_load_graph and validates them the same way
+ * (synchronous).  base must outlive the derived handle.
+ */
+rp_status rp_graph_derive(rp_graph_t base, const int32_t* nbr, const int32_t* deg,
+                          int32_t r_max, void* stream, rp_graph_t* out);
+
+/*
+ * rp_prune -- RP-Tuning of the whole graph at one (alpha, R): for every
+ * vertex p, RobustPrune(p, N_out(p), alpha, R) (Algorithm 1; Section 3 with a
+ * finite degree bound).  R >= 1; R >= deg means no bound in effect.
+ *   out_nbr: n x R int32, row p receives the kept ids in the order Algorithm 1
+ *            adds them (ascending (S(p, .), id)), padded with -1.
+ *   out_deg: n int32, the kept counts.
+ * Outputs must not alias the graph's arrays.  Uses the batched kernels.
+ */
+rp_status rp_prune(rp_graph_t g, rp_alpha alpha, int32_t R, int32_t* out_nbr,
+                   int32_t* out_deg, void* stream);
+
+/*
+ * rp_prune_sweep -- RP-Tuning at several (alpha, R) from one pass over the
+ * graph: n_a alphas x n_R degree bounds, output index o = ia * n_R + iR.
+ *   alphas : host array of n_a (1 <= n_a <= 8).
+ *   Rs     : host array of n_R (1 <= n_R <= 4), each >= 1.
+ *   out_nbr: host array of n_a*n_R device pointers, output o is n x Rs[iR].
+ *   out_deg: host array of n_a*n_R device pointers, each n int32.
+ * Every output equals rp_prune at its own (alpha, R).
+ */
+rp_status rp_prune_sweep(rp_graph_t g, const rp_alpha* alphas, int32_t n_a,
+                         const int32_t* Rs, int32_t n_R, int32_t* const* out_nbr,
+                         int32_t* const* out_deg, void* stream);
+
+/*
+ * rp_prune_plain -- the same result as rp_prune from the plain baseline
+ * kernel: one workgroup per vertex, direct-difference distances evaluated
+ * lazily (FP32 with an FP64 recheck near the threshold for float32 data,
+ * exact integers for uint8), no shared gather across alphas.  Kept as the
+ * comparison point for the batched kernels.
+ */
+rp_status rp_prune_plain(rp_graph_t g, rp_alpha alpha, int32_t R, int32_t* out_nbr,
+                         int32_t* out_deg, void* stream);
+
+/*
+ * rp_search -- GreedySearch(s, q, k, L) (Algorithm 2) from the graph's start
+ * vertex for nq queries.
+ *   queries : nq x d, same dtype as the points.   1 <= k <= L <= 1024.
+ *   out_ids : nq x k int32, the k closest ids of the final list by (S, id),
+ *             padded with -1 when the list holds fewer than k.
+ *   out_dist: nq x k FP64 squared distances (nullable; -1 where padded).
+ *   out_hops: nq int32, |V| = the number of expanded vertices (nullable).
+ */
+rp_status rp_search(rp_graph_t g, const void* queries, int64_t nq, int32_t k, int32_t L,
+                    int32_t* out_ids, double* out_dist, int32_t* out_hops, void* stream);
+
+/*
+ * rp_read_counters -- copy the graph's device counters to *out (host) and,
+ * if reset != 0, zero them.  Synchronises `stream`.
+ */
+rp_status rp_read_counters(rp_graph_t g, rp_counters* out, int32_t reset, void* stream);
+
+/* rp_free_graph -- release a handle (NULL is ignored).  Synchronises the
+ * device; the caller's arrays are not freed. */
+void rp_free_graph(rp_graph_t g);
+
+/* rp_last_error -- message of the calling thread's last failure ("" if none). */
+const char* rp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RP_H */

@@ -1,0 +1,34 @@
+// k_validate.hip -- adjacency validation at load time: every degree must lie in
+// [0, r_max] and every listed id in [0, n).  One lane per vertex; failures are
+// counted into DevCounters::errors.
+#include "dev_common.h"
+
+namespace rp {
+
+__global__ void validate_kernel(GraphView g, DevCounters* ctr) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool bad = false;
+  if (p < g.n) {
+    const int m = g.deg[p];
+    if (m < 0 || m > g.r_max) {
+      bad = true;
+    } else {
+      const int32_t* row = g.nbr + p * g.r_max;
+      for (int t = 0; t < m; ++t) {
+        int id = row[t];
+        if (id < 0 || (int64_t)id >= g.n) bad = true;
+      }
+    }
+  }
+  unsigned long long cnt = __popcll(__ballot(bad));
+  if ((threadIdx.x & (kWave - 1)) == 0 && cnt) atomicAdd(&ctr->errors, cnt);
+}
+
+hipError_t launch_validate(const GraphView& g, DevCounters* ctr, hipStream_t s) {
+  const int block = 256;
+  const int64_t grid = (g.n + block - 1) / block;
+  hipLaunchKernelGGL(validate_kernel, dim3((unsigned)grid), dim3(block), 0, s, g, ctr);
+  return hipGetLastError();
+}
+
+}  // namespace rp

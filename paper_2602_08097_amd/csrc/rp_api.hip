@@ -1,0 +1,276 @@
+// rp_api.hip -- the C-ABI (include/rp.h): argument checks, handle lifetime,
+// dispatch to the kernels.  Every device array is checked on the host to lie
+// inside a device allocation large enough for the sizes given, so that a
+// wrong size or a host pointer becomes RP_EINVAL instead of a GPU fault.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "rp_internal.h"
+
+struct rp_graph {
+  rp::GraphView view;
+  rp::DevCounters* ctr;
+  rp_graph* base;  // non-null for derived handles
+  int device;
+};
+
+namespace {
+
+thread_local char g_err[512];
+
+rp_status fail(rp_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+rp_status ok() {
+  g_err[0] = 0;
+  return RP_OK;
+}
+
+// Is [p, p + bytes) inside one device allocation?
+bool device_range(const void* p, size_t bytes) {
+  if (!p) return false;
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged) return false;
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  const char* b = (const char*)base;
+  const char* q = (const char*)p;
+  return q >= b && (size_t)(q - b) + bytes <= size;
+}
+
+size_t elem_size(int32_t dt) { return dt == RP_U8 ? 1 : 4; }
+
+rp_status check_launch(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(RP_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+  return RP_OK;
+}
+
+rp_status validate_adjacency(const rp::GraphView& v, rp::DevCounters* ctr, hipStream_t s) {
+  if (!device_range(v.nbr, (size_t)v.n * v.r_max * 4))
+    return fail(RP_EINVAL, "nbr is not a device array of n*r_max int32");
+  if (!device_range(v.deg, (size_t)v.n * 4))
+    return fail(RP_EINVAL, "deg is not a device array of n int32");
+  rp::DevCounters zero = {};
+  hipError_t e = hipMemcpyAsync(ctr, &zero, sizeof(zero), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return check_launch(e, "counter reset");
+  rp_status st = check_launch(rp::launch_validate(v, ctr, s), "validate");
+  if (st != RP_OK) return st;
+  rp::DevCounters host = {};
+  e = hipMemcpyAsync(&host, ctr, sizeof(host), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return check_launch(e, "validate readback");
+  // leave the counters at zero for the graph's own use
+  e = hipMemcpyAsync(ctr, &zero, sizeof(zero), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return check_launch(e, "counter reset");
+  if (host.errors)
+    return fail(RP_ERANGE, "%llu vertices have a degree outside [0, r_max] or an id outside [0, n)",
+                (unsigned long long)host.errors);
+  return RP_OK;
+}
+
+rp_status check_alpha(rp_alpha a) {
+  if (a.den < 1 || a.num < a.den || a.num > 65535)
+    return fail(RP_EINVAL, "alpha must be num/den with 1 <= den <= num <= 65535 (got %d/%d)",
+                a.num, a.den);
+  return RP_OK;
+}
+
+rp_status check_outputs(const rp_graph* g, int32_t R, const int32_t* out_nbr,
+                        const int32_t* out_deg) {
+  if (R < 1) return fail(RP_EINVAL, "R must be >= 1 (got %d)", R);
+  if (!device_range(out_nbr, (size_t)g->view.n * R * 4))
+    return fail(RP_EINVAL, "out_nbr is not a device array of n*R int32");
+  if (!device_range(out_deg, (size_t)g->view.n * 4))
+    return fail(RP_EINVAL, "out_deg is not a device array of n int32");
+  const char* a = (const char*)out_nbr;
+  const char* b = (const char*)g->view.nbr;
+  size_t la = (size_t)g->view.n * R * 4, lb = (size_t)g->view.n * g->view.r_max * 4;
+  if (a < b + lb && b < a + la) return fail(RP_EINVAL, "out_nbr overlaps the graph's nbr");
+  return RP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rp_last_error(void) { return g_err; }
+
+rp_status rp_load_graph(const void* points, int32_t dtype, int64_t n, int32_t d,
+                        const int32_t* nbr, const int32_t* deg, int32_t r_max, int32_t start,
+                        void* stream, rp_graph_t* out) {
+  if (!out) return fail(RP_EINVAL, "out is null");
+  *out = nullptr;
+  if (dtype != RP_U8 && dtype != RP_F32) return fail(RP_EINVAL, "dtype must be RP_U8 or RP_F32");
+  if (n < 1 || n >= (1ll << 31)) return fail(RP_EINVAL, "n must be in [1, 2^31)");
+  if (d < 1 || d > rp::kMaxDim) return fail(RP_EINVAL, "d must be in [1, %d]", rp::kMaxDim);
+  if (r_max < 1 || r_max > rp::kMaxRmax)
+    return fail(RP_EINVAL, "r_max must be in [1, %d]", rp::kMaxRmax);
+  if (start < 0 || (int64_t)start >= n) return fail(RP_ERANGE, "start outside [0, n)");
+  if (!device_range(points, (size_t)n * d * elem_size(dtype)))
+    return fail(RP_EINVAL, "points is not a device array of n*d elements");
+  rp_graph* g = new (std::nothrow) rp_graph();
+  if (!g) return fail(RP_ENOMEM, "host allocation failed");
+  g->view = {points, dtype, n, d, nbr, deg, r_max, start};
+  g->base = nullptr;
+  if (hipGetDevice(&g->device) != hipSuccess) {
+    delete g;
+    return fail(RP_EDEVICE, "hipGetDevice failed");
+  }
+  if (hipMalloc((void**)&g->ctr, sizeof(rp::DevCounters)) != hipSuccess) {
+    (void)hipGetLastError();
+    delete g;
+    return fail(RP_ENOMEM, "hipMalloc of counters failed");
+  }
+  rp_status st = validate_adjacency(g->view, g->ctr, (hipStream_t)stream);
+  if (st != RP_OK) {
+    (void)hipFree(g->ctr);
+    delete g;
+    return st;
+  }
+  *out = g;
+  return ok();
+}
+
+rp_status rp_graph_derive(rp_graph_t base, const int32_t* nbr, const int32_t* deg, int32_t r_max,
+                          void* stream, rp_graph_t* out) {
+  if (!out) return fail(RP_EINVAL, "out is null");
+  *out = nullptr;
+  if (!base) return fail(RP_ESTATE, "base is null");
+  if (r_max < 1 || r_max > rp::kMaxRmax)
+    return fail(RP_EINVAL, "r_max must be in [1, %d]", rp::kMaxRmax);
+  rp_graph* g = new (std::nothrow) rp_graph();
+  if (!g) return fail(RP_ENOMEM, "host allocation failed");
+  g->view = base->view;
+  g->view.nbr = nbr;
+  g->view.deg = deg;
+  g->view.r_max = r_max;
+  g->base = base;
+  g->device = base->device;
+  if (hipMalloc((void**)&g->ctr, sizeof(rp::DevCounters)) != hipSuccess) {
+    (void)hipGetLastError();
+    delete g;
+    return fail(RP_ENOMEM, "hipMalloc of counters failed");
+  }
+  rp_status st = validate_adjacency(g->view, g->ctr, (hipStream_t)stream);
+  if (st != RP_OK) {
+    (void)hipFree(g->ctr);
+    delete g;
+    return st;
+  }
+  *out = g;
+  return ok();
+}
+
+rp_status rp_prune_plain(rp_graph_t g, rp_alpha alpha, int32_t R, int32_t* out_nbr,
+                         int32_t* out_deg, void* stream) {
+  if (!g) return fail(RP_ESTATE, "graph is null");
+  rp_status st = check_alpha(alpha);
+  if (st != RP_OK) return st;
+  st = check_outputs(g, R, out_nbr, out_deg);
+  if (st != RP_OK) return st;
+  st = check_launch(rp::launch_prune_plain(g->view, (uint32_t)alpha.num * alpha.num,
+                                           (uint32_t)alpha.den * alpha.den, R, out_nbr, out_deg,
+                                           g->ctr, (hipStream_t)stream),
+                    "prune_plain");
+  return st == RP_OK ? ok() : st;
+}
+
+rp_status rp_prune_sweep(rp_graph_t g, const rp_alpha* alphas, int32_t n_a, const int32_t* Rs,
+                         int32_t n_R, int32_t* const* out_nbr, int32_t* const* out_deg,
+                         void* stream) {
+  if (!g) return fail(RP_ESTATE, "graph is null");
+  if (!alphas || !Rs || !out_nbr || !out_deg) return fail(RP_EINVAL, "null host array");
+  if (n_a < 1 || n_a > rp::kMaxAlphas)
+    return fail(RP_EINVAL, "n_a must be in [1, %d]", rp::kMaxAlphas);
+  if (n_R < 1 || n_R > rp::kMaxRs) return fail(RP_EINVAL, "n_R must be in [1, %d]", rp::kMaxRs);
+  rp::SweepArgs a = {};
+  a.n_alpha = n_a;
+  a.n_out = n_a * n_R;
+  for (int i = 0; i < n_a; ++i) {
+    rp_status st = check_alpha(alphas[i]);
+    if (st != RP_OK) return st;
+    a.num2[i] = (uint32_t)alphas[i].num * alphas[i].num;
+    a.den2[i] = (uint32_t)alphas[i].den * alphas[i].den;
+  }
+  for (int ia = 0; ia < n_a; ++ia)
+    for (int ir = 0; ir < n_R; ++ir) {
+      const int o = ia * n_R + ir;
+      rp_status st = check_outputs(g, Rs[ir], out_nbr[o], out_deg[o]);
+      if (st != RP_OK) return st;
+      a.out[o] = {out_nbr[o], out_deg[o], Rs[ir], ia};
+    }
+  rp_status st = check_launch(rp::launch_prune_batched(g->view, a, g->ctr, (hipStream_t)stream),
+                              "prune_batched");
+  return st == RP_OK ? ok() : st;
+}
+
+rp_status rp_prune(rp_graph_t g, rp_alpha alpha, int32_t R, int32_t* out_nbr, int32_t* out_deg,
+                   void* stream) {
+  return rp_prune_sweep(g, &alpha, 1, &R, 1, &out_nbr, &out_deg, stream);
+}
+
+rp_status rp_search(rp_graph_t g, const void* queries, int64_t nq, int32_t k, int32_t L,
+                    int32_t* out_ids, double* out_dist, int32_t* out_hops, void* stream) {
+  if (!g) return fail(RP_ESTATE, "graph is null");
+  if (nq < 0 || nq >= (1ll << 31)) return fail(RP_EINVAL, "nq must be in [0, 2^31)");
+  if (k < 1 || L < k || L > rp::kMaxL)
+    return fail(RP_EINVAL, "need 1 <= k <= L <= %d (got k=%d, L=%d)", rp::kMaxL, k, L);
+  if (nq == 0) return ok();
+  const rp::GraphView& v = g->view;
+  if (!device_range(queries, (size_t)nq * v.d * elem_size(v.dtype)))
+    return fail(RP_EINVAL, "queries is not a device array of nq*d elements");
+  if (!device_range(out_ids, (size_t)nq * k * 4))
+    return fail(RP_EINVAL, "out_ids is not a device array of nq*k int32");
+  if (out_dist && !device_range(out_dist, (size_t)nq * k * 8))
+    return fail(RP_EINVAL, "out_dist is not a device array of nq*k double");
+  if (out_hops && !device_range(out_hops, (size_t)nq * 4))
+    return fail(RP_EINVAL, "out_hops is not a device array of nq int32");
+  rp_status st = check_launch(
+      rp::launch_search(v, queries, nq, k, L, out_ids, out_dist, out_hops, (hipStream_t)stream),
+      "search");
+  return st == RP_OK ? ok() : st;
+}
+
+rp_status rp_read_counters(rp_graph_t g, rp_counters* out, int32_t reset, void* stream) {
+  if (!g) return fail(RP_ESTATE, "graph is null");
+  if (!out) return fail(RP_EINVAL, "out is null");
+  rp::DevCounters host = {};
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(&host, g->ctr, sizeof(host), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return check_launch(e, "counter readback");
+  out->nodes = (int64_t)host.nodes;
+  out->pairs = (int64_t)host.pairs;
+  out->rechecks = (int64_t)host.rechecks;
+  if (reset) {
+    rp::DevCounters zero = {};
+    e = hipMemcpyAsync(g->ctr, &zero, sizeof(zero), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return check_launch(e, "counter reset");
+  }
+  return ok();
+}
+
+void rp_free_graph(rp_graph_t g) {
+  if (!g) return;
+  (void)hipDeviceSynchronize();
+  (void)hipFree(g->ctr);
+  delete g;
+}
+
+}  // extern "C"

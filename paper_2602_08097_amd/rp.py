@@ -1,0 +1,202 @@
+"""Thin Python binding of the C-ABI in include/rp.h (ctypes; argument
+marshalling only -- every step of pruning and search runs in the HIP kernels).
+
+Tensors must be CUDA (HIP) tensors on the current device; the calls enqueue on
+torch's current stream unless a stream is given.  The binding raises if the
+HIP library is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Iterable, List, Optional, Sequence, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "librp.so")
+
+RP_U8 = 1
+RP_F32 = 2
+_STATUS = {0: "RP_OK", 1: "RP_EINVAL", 2: "RP_ERANGE", 3: "RP_ENOMEM", 4: "RP_EDEVICE",
+           5: "RP_ESTATE"}
+
+
+class RPError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Alpha(C.Structure):
+    _fields_ = [("num", C.c_int32), ("den", C.c_int32)]
+
+
+class Counters(C.Structure):
+    _fields_ = [("nodes", C.c_int64), ("pairs", C.c_int64), ("rechecks", C.c_int64)]
+
+
+EXPORTS = ["rp_load_graph", "rp_graph_derive", "rp_prune", "rp_prune_sweep", "rp_prune_plain",
+           "rp_search", "rp_read_counters", "rp_free_graph", "rp_last_error"]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load librp.so (raises OSError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OSError(f"HIP library not built: {path} (run __graft_entry__.build())")
+    lib = C.CDLL(path)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    lib.rp_load_graph.restype = i32
+    lib.rp_load_graph.argtypes = [vp, i32, i64, i32, vp, vp, i32, i32, vp, C.POINTER(vp)]
+    lib.rp_graph_derive.restype = i32
+    lib.rp_graph_derive.argtypes = [vp, vp, vp, i32, vp, C.POINTER(vp)]
+    lib.rp_prune.restype = i32
+    lib.rp_prune.argtypes = [vp, Alpha, i32, vp, vp, vp]
+    lib.rp_prune_plain.restype = i32
+    lib.rp_prune_plain.argtypes = [vp, Alpha, i32, vp, vp, vp]
+    lib.rp_prune_sweep.restype = i32
+    lib.rp_prune_sweep.argtypes = [vp, C.POINTER(Alpha), i32, C.POINTER(i32), i32,
+                                   C.POINTER(vp), C.POINTER(vp), vp]
+    lib.rp_search.restype = i32
+    lib.rp_search.argtypes = [vp, vp, i64, i32, i32, vp, vp, vp, vp]
+    lib.rp_read_counters.restype = i32
+    lib.rp_read_counters.argtypes = [vp, C.POINTER(Counters), i32, vp]
+    lib.rp_free_graph.restype = None
+    lib.rp_free_graph.argtypes = [vp]
+    lib.rp_last_error.restype = C.c_char_p
+    lib.rp_last_error.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise RPError(rc, _lib.rp_last_error().decode())
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.uint8:
+        return RP_U8
+    if t.dtype == torch.float32:
+        return RP_F32
+    raise TypeError(f"points must be uint8 or float32, got {t.dtype}")
+
+
+def _need_cuda(*ts):
+    for t in ts:
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise ValueError("arguments must be contiguous device tensors")
+
+
+def as_alpha(a) -> Tuple[int, int]:
+    """(num, den) from a tuple or a fractions.Fraction."""
+    if isinstance(a, tuple):
+        return int(a[0]), int(a[1])
+    return int(a.numerator), int(a.denominator)
+
+
+class Graph:
+    """A borrowed point set + adjacency registered with the library.
+
+    The tensors passed in are kept referenced by this object so that they
+    outlive the handle."""
+
+    def __init__(self, points: torch.Tensor, nbr: torch.Tensor, deg: torch.Tensor, start: int,
+                 stream=None, _base: "Graph" = None):
+        lib = load_library()
+        _need_cuda(points, nbr, deg)
+        if nbr.dtype != torch.int32 or deg.dtype != torch.int32:
+            raise TypeError("nbr and deg must be int32")
+        self.points, self.nbr, self.deg = points, nbr, deg
+        self.n, self.d = points.shape
+        self.r_max = nbr.shape[1]
+        self.start = int(start)
+        self._base = _base
+        h = C.c_void_p()
+        if _base is None:
+            rc = lib.rp_load_graph(points.data_ptr(), _dtype_code(points), self.n, self.d,
+                                   nbr.data_ptr(), deg.data_ptr(), self.r_max, self.start,
+                                   _stream_ptr(stream), C.byref(h))
+        else:
+            rc = lib.rp_graph_derive(_base.handle, nbr.data_ptr(), deg.data_ptr(), self.r_max,
+                                     _stream_ptr(stream), C.byref(h))
+        _check(rc)
+        self.handle = h
+
+    def derive(self, nbr: torch.Tensor, deg: torch.Tensor, stream=None) -> "Graph":
+        return Graph(self.points, nbr, deg, self.start, stream, _base=self)
+
+    def _outs(self, R: int):
+        dev = self.points.device
+        return (torch.empty((self.n, R), dtype=torch.int32, device=dev),
+                torch.empty(self.n, dtype=torch.int32, device=dev))
+
+    def prune(self, alpha, R: int, out=None, stream=None):
+        num, den = as_alpha(alpha)
+        nb, dg = out if out is not None else self._outs(R)
+        _need_cuda(nb, dg)
+        _check(_lib.rp_prune(self.handle, Alpha(num, den), int(R), nb.data_ptr(), dg.data_ptr(),
+                             _stream_ptr(stream)))
+        return nb, dg
+
+    def prune_plain(self, alpha, R: int, out=None, stream=None):
+        num, den = as_alpha(alpha)
+        nb, dg = out if out is not None else self._outs(R)
+        _need_cuda(nb, dg)
+        _check(_lib.rp_prune_plain(self.handle, Alpha(num, den), int(R), nb.data_ptr(),
+                                   dg.data_ptr(), _stream_ptr(stream)))
+        return nb, dg
+
+    def prune_sweep(self, alphas: Sequence, Rs: Sequence[int], outs=None, stream=None):
+        """Returns a list of (nbr, deg) in order o = ia * len(Rs) + iR."""
+        al = [as_alpha(a) for a in alphas]
+        na, nr = len(al), len(Rs)
+        if outs is None:
+            outs = [self._outs(Rs[o % nr]) for o in range(na * nr)]
+        A = (Alpha * na)(*[Alpha(a, b) for a, b in al])
+        RR = (C.c_int32 * nr)(*[int(r) for r in Rs])
+        NB = (C.c_void_p * (na * nr))(*[o[0].data_ptr() for o in outs])
+        DG = (C.c_void_p * (na * nr))(*[o[1].data_ptr() for o in outs])
+        _check(_lib.rp_prune_sweep(self.handle, A, na, RR, nr, NB, DG, _stream_ptr(stream)))
+        return outs
+
+    def search(self, Q: torch.Tensor, k: int, L: int, want_dist: bool = True, stream=None):
+        _need_cuda(Q)
+        if Q.dtype != self.points.dtype or Q.shape[1] != self.d:
+            raise ValueError("queries must match the points' dtype and dimension")
+        nq = Q.shape[0]
+        dev = self.points.device
+        ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+        dist = torch.empty((nq, k), dtype=torch.float64, device=dev) if want_dist else None
+        hops = torch.empty(nq, dtype=torch.int32, device=dev)
+        _check(_lib.rp_search(self.handle, Q.data_ptr(), nq, int(k), int(L), ids.data_ptr(),
+                              dist.data_ptr() if dist is not None else None, hops.data_ptr(),
+                              _stream_ptr(stream)))
+        return ids, dist, hops
+
+    def counters(self, reset: bool = False, stream=None) -> dict:
+        c = Counters()
+        _check(_lib.rp_read_counters(self.handle, C.byref(c), 1 if reset else 0,
+                                     _stream_ptr(stream)))
+        return {"nodes": c.nodes, "pairs": c.pairs, "rechecks": c.rechecks}
+
+    def free(self):
+        if getattr(self, "handle", None) is not None and self.handle.value is not None:
+            _lib.rp_free_graph(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -1,0 +1,59 @@
+"""Host-only checks of the C-ABI library (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rp.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rp_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_abi():
+    names = _declared()
+    for want in ("rp_load_graph", "rp_prune", "rp_prune_sweep", "rp_search", "rp_free_graph",
+                 "rp_last_error"):
+        assert want in names
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    from paper_2602_08097_amd import rp
+
+    if not os.path.exists(rp.LIB_PATH):
+        pytest.fail("librp.so is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(rp.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert sorted(rp.EXPORTS) == _declared()
+    lib.rp_last_error.restype = ctypes.c_char_p
+    assert lib.rp_last_error() == b""
+
+
+def test_null_arguments_are_rejected_without_a_device():
+    from paper_2602_08097_amd import rp
+
+    lib = rp.load_library()
+    h = ctypes.c_void_p()
+    assert lib.rp_load_graph(None, 1, 10, 4, None, None, 4, 0, None, ctypes.byref(h)) == 1
+    assert b"points" in lib.rp_last_error()
+    assert lib.rp_load_graph(None, 7, 10, 4, None, None, 4, 0, None, ctypes.byref(h)) == 1
+    assert b"dtype" in lib.rp_last_error()
+    assert lib.rp_load_graph(None, 1, 10, 4, None, None, 4, 10, None, ctypes.byref(h)) == 2
+    assert lib.rp_prune(None, rp.Alpha(6, 5), 4, None, None, None) == 5
+
+
+def test_oracle_library_is_separate():
+    """The oracle is its own gcc-built library; it shares no source with csrc/."""
+    import oracle
+
+    assert os.path.dirname(oracle.lib_path()) != os.path.join(ROOT, "paper_2602_08097_amd")
+    csrc = os.path.join(ROOT, "paper_2602_08097_amd", "csrc")
+    for f in os.listdir(csrc):
+        text = open(os.path.join(csrc, f)).read()
+        assert "rpo" not in text and "oracle" not in text.lower(), f

@@ -1,0 +1,224 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle.
+
+Pruned edge lists must be identical element by element (bit-exact ids and
+degrees); search ids, squared distances and visited counts must be identical.
+Inputs are seeded synthetic workloads (workloads/), scaled so the oracle runs
+in seconds while spanning many tiles and ragged tails.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _graph(X, nbr, deg, start):
+    from paper_2602_08097_amd import Graph
+
+    dev = _dev()
+    return Graph(torch.from_numpy(np.ascontiguousarray(X)).to(dev),
+                 torch.from_numpy(np.ascontiguousarray(nbr, dtype=np.int32)).to(dev),
+                 torch.from_numpy(np.ascontiguousarray(deg, dtype=np.int32)).to(dev), start)
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+_BASE = {}
+
+
+def _oracle_base(w):
+    """The oracle's base graph (RobustPrune of the K-NN lists), cached."""
+    key = (w.spec.name, w.X.shape[0])
+    if key not in _BASE:
+        spec = w.spec
+        o_nbr, o_deg, _ = oracle.prune_graph(w.X, w.knn, w.knn_deg, *spec.base_alpha, spec.base_R)
+        _BASE[key] = (o_nbr, o_deg)
+    return _BASE[key]
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    _dev()
+    return workloads.build("tiny")  # 10,000 x 32 float32, 64-NN lists
+
+
+@pytest.fixture(scope="module")
+def sift_small():
+    dev = _dev()
+    return workloads.build("sift_u8", n=20_000, nq=200, device=dev)
+
+
+def _check_sweep(w, g_base, base_nbr, base_deg, variant):
+    spec = w.spec
+    nr = len(spec.Rs)
+    if variant == "sweep":
+        outs = g_base.prune_sweep(spec.sweep, spec.Rs)
+    else:
+        outs = []
+        for a in spec.sweep:
+            for R in spec.Rs:
+                outs.append(g_base.prune(a, R) if variant == "prune" else g_base.prune_plain(a, R))
+    for o, (nb, dg) in enumerate(outs):
+        a, R = spec.sweep[o // nr], spec.Rs[o % nr]
+        e_nbr, e_deg, _ = oracle.prune_graph(w.X, base_nbr, base_deg, *a, R)
+        got_nbr, got_deg = _np(nb), _np(dg)
+        bad = np.nonzero((got_nbr != e_nbr).any(axis=1) | (got_deg != e_deg))[0]
+        assert bad.size == 0, f"{variant} alpha={a} R={R}: {bad.size} rows differ, first {bad[:5]}"
+
+
+@pytest.mark.parametrize("variant", ["sweep", "plain"])
+def test_tiny_float32_all_nodes(tiny, variant):
+    w, spec = tiny, tiny.spec
+    g0 = _graph(w.X, w.knn, w.knn_deg, w.start)
+    nb, dg = (g0.prune if variant == "sweep" else g0.prune_plain)(spec.base_alpha, spec.base_R)
+    o_nbr, o_deg = _oracle_base(w)
+    assert np.array_equal(_np(nb), o_nbr)
+    assert np.array_equal(_np(dg), o_deg)
+    g = g0.derive(nb, dg)
+    _check_sweep(w, g, o_nbr, o_deg, variant)
+
+
+@pytest.mark.parametrize("variant", ["sweep", "plain"])
+def test_sift_u8_all_nodes(sift_small, variant):
+    w, spec = sift_small, sift_small.spec
+    g0 = _graph(w.X, w.knn, w.knn_deg, w.start)
+    nb, dg = (g0.prune if variant == "sweep" else g0.prune_plain)(spec.base_alpha, spec.base_R)
+    o_nbr, o_deg = _oracle_base(w)
+    assert np.array_equal(_np(nb), o_nbr)
+    assert np.array_equal(_np(dg), o_deg)
+    g = g0.derive(nb, dg)
+    _check_sweep(w, g, o_nbr, o_deg, variant)
+
+
+def test_tiny_search_matches_oracle(tiny):
+    w, spec = tiny, tiny.spec
+    o_nbr, o_deg = _oracle_base(w)
+    g = _graph(w.X, o_nbr, o_deg, w.start)
+    Q = torch.from_numpy(w.Q).to(_dev())
+    for L in (spec.Ls[0], 10, 100):
+        k = min(spec.k, L)
+        ids, dist, hops = g.search(Q, k, L)
+        e_ids, e_dist, e_hops = oracle.search(w.X, o_nbr, o_deg, w.start, w.Q, k, L)
+        assert np.array_equal(_np(ids), e_ids)
+        assert np.array_equal(_np(dist), e_dist)
+        assert np.array_equal(_np(hops), e_hops)
+    gt = oracle.groundtruth(w.X, w.Q, spec.k)
+    ids, _, _ = g.search(Q, spec.k, spec.Ls[0])
+    e_ids, _, _ = oracle.search(w.X, o_nbr, o_deg, w.start, w.Q, spec.k, spec.Ls[0])
+    assert oracle.recall_at_k(_np(ids), gt, spec.k) == oracle.recall_at_k(e_ids, gt, spec.k)
+
+
+def test_sift_search_matches_oracle(sift_small):
+    w, spec = sift_small, sift_small.spec
+    o_nbr, o_deg = _oracle_base(w)
+    g = _graph(w.X, o_nbr, o_deg, w.start)
+    Q = torch.from_numpy(w.Q).to(_dev())
+    for L in (100, 150):
+        ids, dist, hops = g.search(Q, spec.k, L)
+        e_ids, e_dist, e_hops = oracle.search(w.X, o_nbr, o_deg, w.start, w.Q, spec.k, L)
+        assert np.array_equal(_np(ids), e_ids)
+        assert np.array_equal(_np(dist), e_dist)
+        assert np.array_equal(_np(hops), e_hops)
+
+
+# --------------------------------------------------------------------------
+# Edge cases
+# --------------------------------------------------------------------------
+
+def _edge_graph(dtype, n, r_max, seed):
+    rng = np.random.default_rng(seed)
+    if dtype == "u8":
+        X = rng.integers(0, 4, (n, 5)).astype(np.uint8)  # duplicates and ties
+    else:
+        X = (rng.integers(-2, 3, (n, 5)) * 0.25).astype(np.float32)
+    nbr = rng.integers(0, n, (n, r_max)).astype(np.int32)   # self ids and repeats
+    deg = rng.integers(0, r_max + 1, n).astype(np.int32)
+    deg[: min(n, 3)] = 0                                     # empty lists
+    if n > 4:
+        deg[4] = r_max
+    return X, nbr, deg
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+@pytest.mark.parametrize("n,r_max", [(1, 1), (2, 3), (70, 7), (300, 65), (257, 130), (200, 256)])
+def test_edge_cases(dtype, n, r_max):
+    X, nbr, deg = _edge_graph(dtype, n, r_max, seed=n * 7 + r_max)
+    g = _graph(X, nbr, deg, 0)
+    alphas = [(1, 1), (11, 10), (3, 2), (65535, 1)]
+    Rs = [1, 2, r_max]
+    outs = g.prune_sweep(alphas, Rs)
+    for o, (nb, dg) in enumerate(outs):
+        a, R = alphas[o // len(Rs)], Rs[o % len(Rs)]
+        e_nbr, e_deg, _ = oracle.prune_graph(X, nbr, deg, *a, R)
+        assert np.array_equal(_np(nb), e_nbr), (a, R)
+        assert np.array_equal(_np(dg), e_deg), (a, R)
+        p_nbr, p_deg = g.prune_plain(a, R)
+        assert np.array_equal(_np(p_nbr), e_nbr), (a, R)
+        assert np.array_equal(_np(p_deg), e_deg)
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_search_edge_cases(dtype):
+    X, nbr, deg = _edge_graph(dtype, 300, 9, seed=5)
+    g = _graph(X, nbr, deg, 4)
+    Q = X[::7].copy()
+    Qt = torch.from_numpy(Q).to(_dev())
+    for k, L in ((1, 1), (5, 5), (10, 64), (10, 65), (50, 300)):
+        ids, dist, hops = g.search(Qt, k, L)
+        e_ids, e_dist, e_hops = oracle.search(X, nbr, deg, 4, Q, k, L)
+        assert np.array_equal(_np(ids), e_ids), (k, L)
+        assert np.array_equal(_np(dist), e_dist), (k, L)
+        assert np.array_equal(_np(hops), e_hops), (k, L)
+
+
+def test_argument_errors_on_device():
+    from paper_2602_08097_amd import RPError
+
+    dev = _dev()
+    X = torch.zeros((10, 4), dtype=torch.uint8, device=dev)
+    nbr = torch.zeros((10, 3), dtype=torch.int32, device=dev)
+    deg = torch.full((10,), 3, dtype=torch.int32, device=dev)
+    bad = nbr.clone()
+    bad[5, 1] = 10
+    from paper_2602_08097_amd import Graph
+
+    with pytest.raises(RPError, match="RP_ERANGE"):
+        Graph(X, bad, deg, 0)
+    baddeg = deg.clone()
+    baddeg[2] = 4
+    with pytest.raises(RPError, match="RP_ERANGE"):
+        Graph(X, nbr, baddeg, 0)
+    g = Graph(X, nbr, deg, 0)
+    with pytest.raises(RPError, match="RP_EINVAL"):
+        g.prune((1, 2), 3)
+    with pytest.raises(RPError, match="RP_EINVAL"):
+        g.prune((6, 5), 0)
+    with pytest.raises(RPError, match="RP_EINVAL"):
+        g.search(torch.zeros((2, 4), dtype=torch.uint8, device=dev), 5, 4)
+    small = torch.empty((5, 3), dtype=torch.int32, device=dev)
+    with pytest.raises(RPError, match="RP_EINVAL"):
+        g.prune((6, 5), 3, out=(small, torch.empty(10, dtype=torch.int32, device=dev)))
+
+
+def test_counters_and_determinism(sift_small):
+    w, spec = sift_small, sift_small.spec
+    g = _graph(w.X, w.knn, w.knn_deg, w.start)
+    g.counters(reset=True)
+    a1 = [tuple(_np(t).tobytes() for t in o) for o in g.prune_sweep(spec.sweep, spec.Rs)]
+    c = g.counters(reset=True)
+    assert c["nodes"] >= w.X.shape[0]
+    assert c["pairs"] > 0
+    a2 = [tuple(_np(t).tobytes() for t in o) for o in g.prune_sweep(spec.sweep, spec.Rs)]
+    assert a1 == a2
