@@ -1,0 +1,275 @@
+#!/usr/bin/env python3
+"""Benchmark: RP-Tuning prune sweep (and GreedySearch) on one MI355X.
+
+One step = one pass of the prune hot path over the whole graph: RobustPrune
+of every vertex's base out-list at every alpha of the sweep (one launch of
+the batched kernel).  Default workload: 1,000,000 uint8 points, d = 128,
+64-component Gaussian mixture; base graph = exact 128-NN lists pruned at
+alpha = 6/5, R = 64; sweep alpha in {23/20, 11/10, 21/20, 1}, R = 64.
+
+Inputs are resident in HBM before the timed region.  The plain one-workgroup
+per-vertex kernel is timed on the same inputs (one launch per alpha), the
+search leg reports QPS and recall on the pruned graphs, and the CPU oracle is
+timed on a bounded node sample on the host.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("RP-Tuning prune nodes/s (+% HBM/MFMA roofline) vs plain FP32; "
+          "search QPS, p99 at equal recall")
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(deg, d, esz, Rs_per_output):
+    """Bytes RP-Tuning must move per sweep: per vertex the list (4(m+1)), the
+    candidate and own rows ((m+1) d e) and every output row (4R + 4)."""
+    import numpy as np
+
+    m = deg.astype(np.int64)
+    per_out = sum(4 * R + 4 for R in Rs_per_output)
+    return int((4 * (m + 1) + (m + 1) * d * esz).sum() + per_out * m.shape[0])
+
+
+def exact_gt_u8(X, Q, k, chunk=1024):
+    """Exact top-k by (S, id) for uint8 data on the GPU (integer keys)."""
+    import torch
+
+    n = X.shape[0]
+    idbits = max(1, int(n - 1).bit_length())
+    Xf = X.float()
+    nx = (X.long() ** 2).sum(1)
+    rows = torch.arange(n, device=X.device, dtype=torch.int64)
+    out = []
+    for a in range(0, Q.shape[0], chunk):
+        q = Q[a:a + chunk]
+        ip = (q.float() @ Xf.T).long()
+        key = (nx[None, :] - 2 * ip + (q.long() ** 2).sum(1)[:, None]) << idbits | rows[None, :]
+        vals, _ = torch.topk(key, k, dim=1, largest=False, sorted=True)
+        out.append((vals & ((1 << idbits) - 1)).to(torch.int32))
+    return torch.cat(out)
+
+
+def recall(ids, gt, k):
+    import torch
+
+    a = ids[:, :k].long()
+    b = gt[:, :k].long()
+    hit = (a[:, :, None] == b[:, None, :]).any(dim=2).sum().item()
+    return hit / (k * a.shape[0])
+
+
+def cpu_baseline(w, spec, budget_s):
+    """The oracle (single thread) on a node sample of the same sweep."""
+    import numpy as np
+
+    import oracle
+
+    nodes = w.sample
+    # the oracle builds its own base rows for the sample from the K-NN lists
+    b_nbr, b_deg, _ = oracle.prune_graph(w.X, w.knn, w.knn_deg, *spec.base_alpha, spec.base_R,
+                                         nodes=nodes)
+    n = w.X.shape[0]
+    full_nbr = np.zeros((n, spec.base_R), np.int32)
+    full_deg = np.zeros(n, np.int32)
+    full_nbr[nodes] = b_nbr
+    full_deg[nodes] = b_deg
+    done = 0
+    t0 = time.perf_counter()
+    chunk = 500
+    while done < len(nodes) and time.perf_counter() - t0 < budget_s:
+        part = nodes[done:done + chunk]
+        for a in spec.sweep:
+            for R in spec.Rs:
+                oracle.prune_graph(w.X, full_nbr, full_deg, *a, R, nodes=part)
+        done += len(part)
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "nodes/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} sampled vertices x {len(spec.sweep)} alphas x {len(spec.Rs)} R "
+                      f"(base rows from the oracle's own RobustPrune of the K-NN lists), "
+                      f"{dt:.1f} s single-threaded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="sift_u8")
+    ap.add_argument("--n", type=int, default=None)
+    ap.add_argument("--nq", type=int, default=None)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-search", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2602_08097_amd import Graph
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    spec = workloads.CONFIGS[args.config]
+    t0 = time.time()
+    w = workloads.build(args.config, n=args.n, nq=args.nq, device=dev)
+    n, d = w.X.shape
+    log(f"workload {spec.name}: n={n} d={d} ({time.time() - t0:.1f} s incl. exact {spec.knn_k}-NN)")
+
+    X = torch.from_numpy(w.X).to(dev)
+    knn = torch.from_numpy(w.knn).to(dev)
+    kdeg = torch.from_numpy(w.knn_deg).to(dev)
+    g_knn = Graph(X, knn, kdeg, w.start)
+    base_nbr, base_deg = g_knn.prune(spec.base_alpha, spec.base_R)
+    torch.cuda.synchronize()
+    g = g_knn.derive(base_nbr, base_deg)
+    deg_np = base_deg.cpu().numpy()
+    log(f"base graph alpha={spec.base_alpha} R={spec.base_R}: mean degree {deg_np.mean():.2f}")
+
+    nr = len(spec.Rs)
+    outs = [g._outs(spec.Rs[o % nr]) for o in range(len(spec.sweep) * nr)]
+    stream = torch.cuda.current_stream()
+
+    # ---- timed batched sweep ---------------------------------------------
+    for _ in range(args.warmup):
+        g.prune_sweep(spec.sweep, spec.Rs, outs=outs)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t_start = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record(stream)
+        g.prune_sweep(spec.sweep, spec.Rs, outs=outs)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    kern_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
+    ms_per_step = wall * 1e3 / args.steps
+    value = n / (wall / args.steps)
+    avg_kernel_ms = float(np.mean(kern_ms))
+    out_degs = [o[1].cpu().numpy() for o in outs]
+    log(f"batched sweep: {ms_per_step:.3f} ms/step, kernel {avg_kernel_ms:.3f} ms avg, "
+        f"{value:.3e} nodes/s; mean out-degree per alpha "
+        f"{[round(float(x.mean()), 2) for x in out_degs]}")
+
+    esz = 1 if w.X.dtype == np.uint8 else 4
+    Rs_out = [spec.Rs[o % nr] for o in range(len(spec.sweep) * nr)]
+    abytes = algorithmic_bytes(deg_np, d, esz, Rs_out)
+    achieved = abytes / (avg_kernel_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "prune_u8_kernel" if w.X.dtype == np.uint8 else "prune_plain_kernel",
+                "algorithmic_bytes_per_launch": abytes,
+                "kernel_ms_avg": round(avg_kernel_ms, 4)}
+
+    # ---- plain kernel on the same inputs ----------------------------------
+    plain = None
+    if not args.no_plain:
+        psteps = max(1, min(3, args.steps))
+        pouts = [g._outs(R) for R in spec.Rs]
+        for a in spec.sweep:  # warm
+            for ir, R in enumerate(spec.Rs):
+                g.prune_plain(a, R, out=pouts[ir])
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        for _ in range(psteps):
+            for a in spec.sweep:
+                for ir, R in enumerate(spec.Rs):
+                    g.prune_plain(a, R, out=pouts[ir])
+        torch.cuda.synchronize()
+        pwall = (time.perf_counter() - tp) / psteps
+        # the plain path agrees with the batched one (last alpha compared)
+        same = bool(torch.equal(pouts[-1][0], outs[-1][0]))
+        plain = {"nodes_per_s": n / pwall, "ms_per_step": pwall * 1e3,
+                 "speedup_batched_vs_plain": (n / (wall / args.steps)) / (n / pwall),
+                 "outputs_identical": same}
+        log(f"plain: {pwall * 1e3:.3f} ms/step, {n / pwall:.3e} nodes/s, identical={same}")
+
+    # ---- search leg --------------------------------------------------------
+    search = None
+    if not args.no_search and w.Q.shape[0] > 0:
+        Q = torch.from_numpy(w.Q).to(dev)
+        k = spec.k
+        gt = exact_gt_u8(X, Q, k) if w.X.dtype == np.uint8 else None
+        res = []
+        graphs = [("base", g, None)]
+        for o in range(0, len(outs), nr):
+            graphs.append((f"alpha={spec.sweep[o // nr][0]}/{spec.sweep[o // nr][1]}",
+                           g.derive(outs[o][0], outs[o][1]), None))
+        for name, gg, _ in graphs:
+            for L in spec.Ls:
+                gg.search(Q, k, L, want_dist=False)
+                torch.cuda.synchronize()
+                lat = []
+                for _ in range(3):
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    ids, _, hops = gg.search(Q, k, L, want_dist=False)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    lat.append(e0.elapsed_time(e1))
+                ms = float(np.median(lat))
+                rec = recall(ids, gt, k) if gt is not None else None
+                res.append({"graph": name, "L": L, "qps": Q.shape[0] / (ms * 1e-3),
+                            "batch_ms_p50": ms, "batch_ms_max": float(np.max(lat)),
+                            "recall_at_k": rec, "mean_hops": float(hops.float().mean().item())})
+                log(f"search {name} L={L}: {Q.shape[0] / (ms * 1e-3):.3e} QPS, recall {rec}")
+        search = {"k": k, "nq": int(Q.shape[0]), "results": res}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(w, spec, args.cpu_budget)
+        log(f"cpu oracle: {cpu['value']:.1f} nodes/s ({cpu['sample']})")
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "nodes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8" if w.X.dtype == np.uint8 else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{spec.name}: {n} x {d} "
+                               f"{'uint8' if esz == 1 else 'float32'} Gaussian mixture, base "
+                               f"exact {spec.knn_k}-NN + RobustPrune alpha={spec.base_alpha[0]}/"
+                               f"{spec.base_alpha[1]} R={spec.base_R}; sweep alpha="
+                               f"{[f'{a}/{b}' for a, b in spec.sweep]} R={list(spec.Rs)}",
+                   "n": n, "d": d, "mean_base_degree": float(deg_np.mean()),
+                   "outputs_per_step": len(outs)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "plain": plain,
+        "search": search,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -136,6 +136,13 @@ class Graph:
     def derive(self, nbr: torch.Tensor, deg: torch.Tensor, stream=None) -> "Graph":
         return Graph(self.points, nbr, deg, self.start, stream, _base=self)
 
+    def _check_out(self, nb: torch.Tensor, dg: torch.Tensor, R: int):
+        _need_cuda(nb, dg)
+        if nb.dtype != torch.int32 or dg.dtype != torch.int32:
+            raise TypeError("outputs must be int32")
+        if tuple(nb.shape) != (self.n, R) or tuple(dg.shape) != (self.n,):
+            raise ValueError(f"outputs must be ({self.n}, {R}) and ({self.n},)")
+
     def _outs(self, R: int):
         dev = self.points.device
         return (torch.empty((self.n, R), dtype=torch.int32, device=dev),
@@ -144,7 +151,7 @@ class Graph:
     def prune(self, alpha, R: int, out=None, stream=None):
         num, den = as_alpha(alpha)
         nb, dg = out if out is not None else self._outs(R)
-        _need_cuda(nb, dg)
+        self._check_out(nb, dg, R)
         _check(_lib.rp_prune(self.handle, Alpha(num, den), int(R), nb.data_ptr(), dg.data_ptr(),
                              _stream_ptr(stream)))
         return nb, dg
@@ -152,7 +159,7 @@ class Graph:
     def prune_plain(self, alpha, R: int, out=None, stream=None):
         num, den = as_alpha(alpha)
         nb, dg = out if out is not None else self._outs(R)
-        _need_cuda(nb, dg)
+        self._check_out(nb, dg, R)
         _check(_lib.rp_prune_plain(self.handle, Alpha(num, den), int(R), nb.data_ptr(),
                                    dg.data_ptr(), _stream_ptr(stream)))
         return nb, dg
@@ -163,6 +170,8 @@ class Graph:
         na, nr = len(al), len(Rs)
         if outs is None:
             outs = [self._outs(Rs[o % nr]) for o in range(na * nr)]
+        for o, (nb, dg) in enumerate(outs):
+            self._check_out(nb, dg, int(Rs[o % nr]))
         A = (Alpha * na)(*[Alpha(a, b) for a, b in al])
         RR = (C.c_int32 * nr)(*[int(r) for r in Rs])
         NB = (C.c_void_p * (na * nr))(*[o[0].data_ptr() for o in outs])

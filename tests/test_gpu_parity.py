@@ -169,6 +169,39 @@ def test_edge_cases(dtype, n, r_max):
         assert np.array_equal(_np(p_deg), e_deg)
 
 
+@pytest.mark.parametrize("d", [16, 48, 128, 256])
+@pytest.mark.parametrize("r_max", [1, 17, 64])
+def test_edge_cases_u8_batched_kernel(d, r_max):
+    """uint8 shapes that take the int8-MFMA batched kernel: ragged and empty
+    lists, self ids, repeated ids, duplicate points, every alpha count."""
+    rng = np.random.default_rng(d * 131 + r_max)
+    n = 500
+    X = rng.integers(0, 256, (n, d)).astype(np.uint8)
+    X[10:20] = X[5]                      # duplicate points (S = 0)
+    X[30:40] = rng.integers(120, 124, (10, d)).astype(np.uint8)  # near-ties
+    nbr = rng.integers(0, n, (n, r_max)).astype(np.int32)
+    nbr[:, 0] = np.arange(n)             # p itself
+    if r_max > 2:
+        nbr[:, 2] = nbr[:, 1]            # repeated id
+    nbr[5, :] = np.arange(10, 10 + r_max) % n
+    deg = rng.integers(0, r_max + 1, n).astype(np.int32)
+    deg[:3] = 0
+    deg[3:8] = r_max
+    g = _graph(X, nbr, deg, 0)
+    all_alphas = [(1, 1), (21, 20), (11, 10), (6, 5), (3, 2), (2, 1), (5, 1), (65535, 1)]
+    for na in (1, 4, 8):
+        alphas = all_alphas[:na] if na < 8 else all_alphas
+        Rs = [r_max, max(1, r_max // 2), 1][: 1 + (na % 3)]
+        outs = g.prune_sweep(alphas, Rs)
+        for o, (nb, dg) in enumerate(outs):
+            a, R = alphas[o // len(Rs)], Rs[o % len(Rs)]
+            e_nbr, e_deg, _ = oracle.prune_graph(X, nbr, deg, *a, R)
+            got = _np(nb)
+            bad = np.nonzero((got != e_nbr).any(axis=1))[0]
+            assert bad.size == 0, (na, a, R, bad[:5], got[bad[:1]], e_nbr[bad[:1]])
+            assert np.array_equal(_np(dg), e_deg), (a, R)
+
+
 @pytest.mark.parametrize("dtype", ["u8", "f32"])
 def test_search_edge_cases(dtype):
     X, nbr, deg = _edge_graph(dtype, 300, 9, seed=5)
@@ -208,8 +241,18 @@ def test_argument_errors_on_device():
     with pytest.raises(RPError, match="RP_EINVAL"):
         g.search(torch.zeros((2, 4), dtype=torch.uint8, device=dev), 5, 4)
     small = torch.empty((5, 3), dtype=torch.int32, device=dev)
-    with pytest.raises(RPError, match="RP_EINVAL"):
+    with pytest.raises(ValueError):
         g.prune((6, 5), 3, out=(small, torch.empty(10, dtype=torch.int32, device=dev)))
+    # host memory passed straight through the C-ABI is refused before any launch
+    import ctypes
+    from paper_2602_08097_amd import rp
+
+    lib = rp.load_library()
+    host_nbr = torch.empty((10, 3), dtype=torch.int32)
+    dev_deg = torch.empty(10, dtype=torch.int32, device=dev)
+    rc = lib.rp_prune(g.handle, rp.Alpha(6, 5), 3, host_nbr.data_ptr(), dev_deg.data_ptr(),
+                      None)
+    assert rc == 1 and b"out_nbr" in lib.rp_last_error()
 
 
 def test_counters_and_determinism(sift_small):
