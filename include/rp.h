@@ -67,9 +67,8 @@ typedef enum {
 
 /* Device-side counters of a graph handle (see rp_read_counters). */
 typedef struct {
-  int64_t nodes;      /* node-prunes completed (nodes x outputs)             */
-  int64_t pairs;      /* candidate pairs decided by the pruning condition    */
-  int64_t rechecks;   /* pairs re-evaluated in canonical FP64 (float32 data) */
+  int64_t nodes;      /* vertex-prunes enqueued (vertices x outputs)            */
+  int64_t rechecks;   /* pairs re-evaluated in canonical FP64 (float32 data)    */
 } rp_counters;
 
 /*

@@ -69,7 +69,7 @@ __global__ __launch_bounds__(64) void prune_plain_kernel(GraphView g, uint32_t n
   for (int r = lane; r < nv; r += kWave) alive[r] = 1;
   __syncthreads();
 
-  unsigned long long pairs = 0, rechecks = 0;
+  unsigned long long rechecks = 0;
   int kept = 0;
   for (int r = 0; r < nv; ++r) {
     if (!alive[r]) continue;  // uniform: read after the barrier
@@ -99,7 +99,6 @@ __global__ __launch_bounds__(64) void prune_plain_kernel(GraphView g, uint32_t n
           prune = dec == 1;
         }
       }
-      ++pairs;
       if (prune) alive[u] = 0;
     }
     __syncthreads();
@@ -107,12 +106,9 @@ __global__ __launch_bounds__(64) void prune_plain_kernel(GraphView g, uint32_t n
   for (int t = kept + lane; t < R; t += kWave) out_nbr[p * R + t] = -1;
   if (lane == 0) out_deg[p] = kept;
 
-  pairs = wave_sum_u64(pairs);
-  rechecks = wave_sum_u64(rechecks);
-  if (lane == 0) {
-    atomicAdd(&ctr->nodes, 1ull);
-    atomicAdd(&ctr->pairs, pairs);
-    if (rechecks) atomicAdd(&ctr->rechecks, rechecks);
+  if (DT == RP_F32) {
+    rechecks = wave_sum_u64(rechecks);
+    if (lane == 0 && rechecks) atomicAdd(&ctr->rechecks, rechecks);
   }
 }
 

@@ -43,6 +43,7 @@ namespace {
 //   S tile: rows 0..31 x 64 columns, rows 32..63 x 32 columns (upper blocks)
 constexpr int kSTileBytes = (32 * 64 + 32 * 32) * 4;  // 12 KiB
 constexpr int kMaxDimU8 = 256;
+constexpr int kGatherBatch = 9;  // 16-byte loads in flight per lane (65 rows x 128 B = 520)
 
 __host__ __device__ constexpr int u_stride(int d) { return d + 16; }
 
@@ -109,17 +110,36 @@ __global__ __launch_bounds__(64) void prune_u8_kernel(GraphView g, SweepArgs a, 
   __syncthreads();
 
   // ---- a2: coalesced gather into LDS (u = x - 128) -----------------------
+  // Every load of a batch is issued before any of its stores so that the
+  // lane's loads are in flight together.
   {
     const int cpr = d >> 4;  // 16-byte chunks per row
     const int total = 65 * cpr;
-    for (int c = lane; c < total; c += 64) {
-      const int row = c / cpr;
-      const int col = c - row * cpr;
-      const int rid = idl[row];
-      uint4 v = make_uint4(0x80808080u, 0x80808080u, 0x80808080u, 0x80808080u);
-      if (rid >= 0) v = *(const uint4*)(X + (int64_t)rid * d + col * 16);
-      v.x ^= 0x80808080u; v.y ^= 0x80808080u; v.z ^= 0x80808080u; v.w ^= 0x80808080u;
-      *(uint4*)(U + row * stride + col * 16) = v;
+    const float inv_cpr = 1.0f / (float)cpr;
+    for (int base = 0; base < total; base += 64 * kGatherBatch) {
+      uint4 buf[kGatherBatch];
+      int dst[kGatherBatch];
+#pragma unroll
+      for (int t = 0; t < kGatherBatch; ++t) {
+        const int c = base + lane + 64 * t;
+        buf[t] = make_uint4(0x80808080u, 0x80808080u, 0x80808080u, 0x80808080u);
+        dst[t] = -1;
+        if (c < total) {
+          const int row = (int)(((float)c + 0.5f) * inv_cpr);
+          const int col = c - row * cpr;
+          const int rid = idl[row];
+          dst[t] = row * stride + col * 16;
+          if (rid >= 0) buf[t] = *(const uint4*)(X + (int64_t)rid * d + col * 16);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < kGatherBatch; ++t) {
+        if (dst[t] >= 0) {
+          uint4 v = buf[t];
+          v.x ^= 0x80808080u; v.y ^= 0x80808080u; v.z ^= 0x80808080u; v.w ^= 0x80808080u;
+          *(uint4*)(U + dst[t]) = v;
+        }
+      }
     }
   }
   __syncthreads();
@@ -276,7 +296,6 @@ __global__ __launch_bounds__(64) void prune_u8_kernel(GraphView g, SweepArgs a, 
     for (int t = cntR + lane; t < R; t += 64) orow[t] = -1;
     if (lane == 0) out.deg[p] = cntR;
   }
-  if (lane == 0) atomicAdd(&ctr->nodes, (unsigned long long)a.n_out);
 }
 
 }  // namespace

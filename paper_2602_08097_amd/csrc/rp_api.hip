@@ -13,6 +13,7 @@ struct rp_graph {
   rp::DevCounters* ctr;
   rp_graph* base;  // non-null for derived handles
   int device;
+  int64_t nodes;   // vertex-prunes enqueued, counted on the host
 };
 
 namespace {
@@ -187,7 +188,9 @@ rp_status rp_prune_plain(rp_graph_t g, rp_alpha alpha, int32_t R, int32_t* out_n
                                            (uint32_t)alpha.den * alpha.den, R, out_nbr, out_deg,
                                            g->ctr, (hipStream_t)stream),
                     "prune_plain");
-  return st == RP_OK ? ok() : st;
+  if (st != RP_OK) return st;
+  g->nodes += g->view.n;
+  return ok();
 }
 
 rp_status rp_prune_sweep(rp_graph_t g, const rp_alpha* alphas, int32_t n_a, const int32_t* Rs,
@@ -216,7 +219,9 @@ rp_status rp_prune_sweep(rp_graph_t g, const rp_alpha* alphas, int32_t n_a, cons
     }
   rp_status st = check_launch(rp::launch_prune_batched(g->view, a, g->ctr, (hipStream_t)stream),
                               "prune_batched");
-  return st == RP_OK ? ok() : st;
+  if (st != RP_OK) return st;
+  g->nodes += g->view.n * a.n_out;
+  return ok();
 }
 
 rp_status rp_prune(rp_graph_t g, rp_alpha alpha, int32_t R, int32_t* out_nbr, int32_t* out_deg,
@@ -254,14 +259,14 @@ rp_status rp_read_counters(rp_graph_t g, rp_counters* out, int32_t reset, void* 
   hipError_t e = hipMemcpyAsync(&host, g->ctr, sizeof(host), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return check_launch(e, "counter readback");
-  out->nodes = (int64_t)host.nodes;
-  out->pairs = (int64_t)host.pairs;
+  out->nodes = g->nodes;
   out->rechecks = (int64_t)host.rechecks;
   if (reset) {
     rp::DevCounters zero = {};
     e = hipMemcpyAsync(g->ctr, &zero, sizeof(zero), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return check_launch(e, "counter reset");
+    g->nodes = 0;
   }
   return ok();
 }

@@ -18,10 +18,8 @@ constexpr int kMaxL = 1024;         // largest search list size
 
 // Device-side counters (mirrors rp_counters).
 struct DevCounters {
-  unsigned long long nodes;
-  unsigned long long pairs;
-  unsigned long long rechecks;
-  unsigned long long errors;  // adjacency validation failures
+  unsigned long long rechecks;  // canonical FP64 re-evaluations
+  unsigned long long errors;    // adjacency validation failures
 };
 
 // One sweep output: alpha as (num^2, den^2) and its degree bound / buffers.

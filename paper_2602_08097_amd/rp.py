@@ -33,7 +33,7 @@ class Alpha(C.Structure):
 
 
 class Counters(C.Structure):
-    _fields_ = [("nodes", C.c_int64), ("pairs", C.c_int64), ("rechecks", C.c_int64)]
+    _fields_ = [("nodes", C.c_int64), ("rechecks", C.c_int64)]
 
 
 EXPORTS = ["rp_load_graph", "rp_graph_derive", "rp_prune", "rp_prune_sweep", "rp_prune_plain",
@@ -197,7 +197,7 @@ class Graph:
         c = Counters()
         _check(_lib.rp_read_counters(self.handle, C.byref(c), 1 if reset else 0,
                                      _stream_ptr(stream)))
-        return {"nodes": c.nodes, "pairs": c.pairs, "rechecks": c.rechecks}
+        return {"nodes": c.nodes, "rechecks": c.rechecks}
 
     def free(self):
         if getattr(self, "handle", None) is not None and self.handle.value is not None:

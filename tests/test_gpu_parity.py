@@ -102,6 +102,52 @@ def test_sift_u8_all_nodes(sift_small, variant):
     _check_sweep(w, g, o_nbr, o_deg, variant)
 
 
+def _sampled_sweep_check(w, X, base_nbr, base_deg, outs, alphas, Rs, nodes):
+    nr = len(Rs)
+    for o, (nb, dg) in enumerate(outs):
+        a, R = alphas[o // nr], Rs[o % nr]
+        e_nbr, e_deg, _ = oracle.prune_graph(X, base_nbr, base_deg, *a, R, nodes=nodes)
+        got_nbr, got_deg = _np(nb)[nodes], _np(dg)[nodes]
+        bad = np.nonzero((got_nbr != e_nbr).any(axis=1) | (got_deg != e_deg))[0]
+        assert bad.size == 0, f"alpha={a} R={R}: {bad.size} sampled rows differ, first {nodes[bad[:5]]}"
+
+
+def test_deep_f32_uneven_degrees():
+    """Deep-1M-shaped recipe at reduced n: unit-normalised float32, d = 96,
+    base RobustPrune at 13/10 then out-degrees cut to t_p ~ U{16..64}, eight
+    alphas per sweep through the FP16-MFMA kernel with FP64 recheck."""
+    dev = _dev()
+    w = workloads.build("deep_f32", n=6000, nq=50, device=dev)
+    spec = w.spec
+    o_nbr, o_deg = _oracle_base(w)
+    o_deg = np.minimum(o_deg, w.targets)            # the oracle's own truncation
+    g0 = _graph(w.X, w.knn, w.knn_deg, w.start)
+    nb, dg = g0.prune(spec.base_alpha, spec.base_R)
+    assert np.array_equal(_np(nb), o_nbr)
+    dg = torch.minimum(dg, torch.from_numpy(w.targets).to(dev))   # the GPU side's truncation
+    g = g0.derive(nb, dg)
+    g.counters(reset=True)
+    outs = g.prune_sweep(spec.sweep, spec.Rs)
+    nodes = w.sample[:1500]
+    _sampled_sweep_check(w, w.X, o_nbr, o_deg, outs, spec.sweep, spec.Rs, nodes)
+    c = g.counters()
+    assert c["nodes"] == w.X.shape[0] * len(spec.sweep)
+
+
+def test_gist_f32_chunked_dimension():
+    """d = 960 (GIST-1M shape) through the d-chunked FP16 path (out-lists of 64)."""
+    dev = _dev()
+    w = workloads.build("gist_f32", n=2500, nq=10, device=dev, knn_k=96)
+    o_nbr, o_deg, _ = oracle.prune_graph(w.X, w.knn, w.knn_deg, 6, 5, 64)
+    g0 = _graph(w.X, w.knn, w.knn_deg, w.start)
+    nb, dg = g0.prune((6, 5), 64)
+    assert np.array_equal(_np(nb), o_nbr)
+    g = g0.derive(nb, dg)
+    alphas, Rs = [(11, 10), (1, 1)], [64, 32]
+    outs = g.prune_sweep(alphas, Rs)
+    _sampled_sweep_check(w, w.X, o_nbr, o_deg, outs, alphas, Rs, w.sample[:600])
+
+
 def test_tiny_search_matches_oracle(tiny):
     w, spec = tiny, tiny.spec
     o_nbr, o_deg = _oracle_base(w)
@@ -202,6 +248,37 @@ def test_edge_cases_u8_batched_kernel(d, r_max):
             assert np.array_equal(_np(dg), e_deg), (a, R)
 
 
+@pytest.mark.parametrize("d", [5, 32, 100])
+def test_edge_cases_f32_batched_kernel(d):
+    """float32 shapes that take the FP16-MFMA kernel: exact ties (values on a
+    1/4 grid make many alpha tests land exactly on the threshold and go to the
+    FP64 recheck), duplicate points, ragged and empty lists, wide dynamic range."""
+    rng = np.random.default_rng(d)
+    n = 400
+    X = (rng.integers(-3, 4, (n, d)) * 0.25).astype(np.float32)
+    X[50:60] = (rng.standard_normal((10, d)) * 1e6).astype(np.float32)
+    X[60:70] = (rng.standard_normal((10, d)) * 1e-6).astype(np.float32)
+    X[10:15] = X[7]
+    nbr = rng.integers(0, n, (n, 64)).astype(np.int32)
+    nbr[:, 3] = np.arange(n)
+    nbr[7, :20] = np.arange(10, 30)
+    deg = rng.integers(0, 65, n).astype(np.int32)
+    deg[:2] = 0
+    g = _graph(X, nbr, deg, 0)
+    alphas = [(1, 1), (21, 20), (6, 5), (3, 2), (2, 1)]
+    Rs = [64, 7]
+    g.counters(reset=True)
+    outs = g.prune_sweep(alphas, Rs)
+    for o, (nb, dg) in enumerate(outs):
+        a, R = alphas[o // len(Rs)], Rs[o % len(Rs)]
+        e_nbr, e_deg, _ = oracle.prune_graph(X, nbr, deg, *a, R)
+        got = _np(nb)
+        bad = np.nonzero((got != e_nbr).any(axis=1))[0]
+        assert bad.size == 0, (a, R, bad[:5], got[bad[:1]], e_nbr[bad[:1]])
+        assert np.array_equal(_np(dg), e_deg), (a, R)
+    assert g.counters()["rechecks"] > 0  # the exact ties went through FP64
+
+
 @pytest.mark.parametrize("dtype", ["u8", "f32"])
 def test_search_edge_cases(dtype):
     X, nbr, deg = _edge_graph(dtype, 300, 9, seed=5)
@@ -261,7 +338,7 @@ def test_counters_and_determinism(sift_small):
     g.counters(reset=True)
     a1 = [tuple(_np(t).tobytes() for t in o) for o in g.prune_sweep(spec.sweep, spec.Rs)]
     c = g.counters(reset=True)
-    assert c["nodes"] >= w.X.shape[0]
-    assert c["pairs"] > 0
+    assert c["nodes"] == w.X.shape[0] * len(spec.sweep) * len(spec.Rs)
+    assert c["rechecks"] == 0  # integer data never needs a recheck
     a2 = [tuple(_np(t).tobytes() for t in o) for o in g.prune_sweep(spec.sweep, spec.Rs)]
     assert a1 == a2
