@@ -4,31 +4,31 @@
 // vertex p at every alpha of a sweep from a single gather of the candidate
 // rows.  For out-lists of at most 64 ids and d a multiple of 16 (d <= 256):
 //
-//  a1  read:   lane t holds the t-th listed id; p itself is dropped here.
-//  a2  gather: rows are staged in LDS as int8 u = x - 128 (the shift leaves
-//              every squared distance unchanged) with coalesced 16-byte loads:
-//              d/16 consecutive lanes read one row.
+//  a1  read:   lane t holds the t-th listed id.
+//  a2  gather: coalesced 16-byte loads, d/16 consecutive lanes per row, all
+//              of a lane's loads in flight together, stored to LDS as int8
+//              u = x - 128 (the shift leaves every difference unchanged).
 //  a3  p-row:  S(p, j) = |u_p|^2 + |u_j|^2 - 2 <u_p, u_j>, exact in int32,
 //              with 4-way int8 dot products.
 //  a4  sort:   a 64-lane bitonic sort of keys (S(p, j), id, slot) packed in
-//              64 bits.  The repeated argmin of Algorithm 1 over a shrinking
-//              candidate set visits the candidates in this order; repeated
-//              ids become adjacent and are dropped.
+//              64 bits, lane exchanges by DPP and swizzles.  The repeated
+//              argmin of Algorithm 1 over a shrinking candidate set visits the
+//              candidates in this order; p and repeated ids are dropped.
 //  a5  Gram:   G = U U^T over the rank-ordered rows on
-//              v_mfma_i32_32x32x32_i8 (exact int32 accumulation); only the
-//              blocks on or above the diagonal are formed, and
-//              S(i, j) = |u_i|^2 + |u_j|^2 - 2 G(i, j) is written to LDS.
+//              v_mfma_i32_32x32x32_i8 (exact int32 accumulation); blocks on
+//              and above the diagonal only; S(i, j) = |u_i|^2 + |u_j|^2
+//              - 2 G(i, j) is written to a 12 KiB LDS tile.
 //  a6  test:   alpha * D(p*, p') <= D(p, p') on squares is
 //              num^2 S(p*, p') <= den^2 S(p, p')  <=>  S(p*, p') <= T(p'),
 //              T(p') = floor(den^2 S(p, p') / num^2), exact for integer S.
-//  a7  greedy: per alpha a 64-bit survivor mask in scalar registers:
-//              p* = lowest surviving rank, kept; its S row is read from LDS
-//              and one ballot of S(p*, .) <= T removes every candidate it
-//              prunes.  All alphas advance in lockstep so their LDS reads
-//              overlap.  The chain stops at the largest R requested for that
-//              alpha; a smaller R is the prefix of the same chain.
-//  a8  write:  the kept ranks of each output are scattered to their
-//              positions (popcount of the kept ranks before them), -1 padded.
+//  a7  greedy: per alpha a 64-bit survivor mask; p* = lowest surviving rank
+//              is kept, its S row is read from LDS and one ballot of
+//              S(p*, .) <= T removes p* itself (S = 0) and every candidate it
+//              prunes.  All alphas advance in lockstep without branches, so
+//              their LDS reads are in flight together.  A chain stops at the
+//              largest R requested for its alpha; a smaller R is a prefix.
+//  a8  write:  kept ranks are scattered to their positions (popcount of the
+//              kept ranks before them), -1 padded.
 #include "dev_common.h"
 
 namespace rp {
@@ -38,43 +38,64 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 
 namespace {
 
-// LDS per wave: max(U tile, S tile) + per-rank squared norms.
-//   U tile: 65 rows (64 candidates + p) of d + 16 bytes (padding staggers banks)
-//   S tile: rows 0..31 x 64 columns, rows 32..63 x 32 columns (upper blocks)
-constexpr int kSTileBytes = (32 * 64 + 32 * 32) * 4;  // 12 KiB
+constexpr int kSTileBytes = 3072 * 4;  // S tile, 12 KiB: the blocks on and above the diagonal
 constexpr int kMaxDimU8 = 256;
 constexpr int kGatherBatch = 9;  // 16-byte loads in flight per lane (65 rows x 128 B = 520)
 
 __host__ __device__ constexpr int u_stride(int d) { return d + 16; }
 
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
-  int lo = __shfl_xor((int)(uint32_t)v, m, 64);
-  int hi = __shfl_xor((int)(uint32_t)(v >> 32), m, 64);
-  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+// Lane exchange with partner lane ^ J (J a power of two).
+template <int J>
+__device__ __forceinline__ int xchg(int v) {
+  if constexpr (J == 1) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+  else if constexpr (J == 2) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+  else if constexpr (J == 4) return __builtin_amdgcn_ds_swizzle(v, 0x101F);
+  else if constexpr (J == 8) return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);
+  else if constexpr (J == 16) return __builtin_amdgcn_ds_swizzle(v, 0x401F);
+  else return __shfl_xor(v, 32, 64);
+}
+
+template <int K, int J>
+__device__ __forceinline__ uint64_t bitonic_step(uint64_t key, int lane) {
+  const int lo = xchg<J>((int)(uint32_t)key);
+  const int hi = xchg<J>((int)(uint32_t)(key >> 32));
+  const uint64_t other = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+  const bool take_min = ((lane & J) == 0) == ((lane & K) == 0);
+  const uint64_t mn = key < other ? key : other;
+  const uint64_t mx = key < other ? other : key;
+  return take_min ? mn : mx;
+}
+
+// Ascending bitonic sort of one 64-bit key per lane across the wavefront.
+__device__ __forceinline__ uint64_t wave_sort(uint64_t k, int lane) {
+  k = bitonic_step<2, 1>(k, lane);
+  k = bitonic_step<4, 2>(k, lane);
+  k = bitonic_step<4, 1>(k, lane);
+  k = bitonic_step<8, 4>(k, lane);
+  k = bitonic_step<8, 2>(k, lane);
+  k = bitonic_step<8, 1>(k, lane);
+  k = bitonic_step<16, 8>(k, lane);
+  k = bitonic_step<16, 4>(k, lane);
+  k = bitonic_step<16, 2>(k, lane);
+  k = bitonic_step<16, 1>(k, lane);
+  k = bitonic_step<32, 16>(k, lane);
+  k = bitonic_step<32, 8>(k, lane);
+  k = bitonic_step<32, 4>(k, lane);
+  k = bitonic_step<32, 2>(k, lane);
+  k = bitonic_step<32, 1>(k, lane);
+  k = bitonic_step<64, 32>(k, lane);
+  k = bitonic_step<64, 16>(k, lane);
+  k = bitonic_step<64, 8>(k, lane);
+  k = bitonic_step<64, 4>(k, lane);
+  k = bitonic_step<64, 2>(k, lane);
+  k = bitonic_step<64, 1>(k, lane);
+  return k;
 }
 
 __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
   int lo = __shfl((int)(uint32_t)v, src, 64);
   int hi = __shfl((int)(uint32_t)(v >> 32), src, 64);
   return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
-}
-
-// Ascending bitonic sort of one 64-bit key per lane across the wavefront.
-__device__ __forceinline__ uint64_t wave_sort(uint64_t key, int lane) {
-#pragma unroll
-  for (int k = 2; k <= 64; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      uint64_t other = shfl_xor_u64(key, j);
-      bool up = (lane & k) == 0;
-      bool lower = (lane & j) == 0;
-      bool take_min = lower == up;
-      uint64_t mn = key < other ? key : other;
-      uint64_t mx = key < other ? other : key;
-      key = take_min ? mn : mx;
-    }
-  }
-  return key;
 }
 
 // floor(den2 * s / num2) for s < 2^28, exact.
@@ -87,31 +108,29 @@ __device__ __forceinline__ int32_t alpha_threshold(uint32_t num2, uint32_t den2,
   return (int32_t)t;
 }
 
-template <int NA>
-__global__ __launch_bounds__(64) void prune_u8_kernel(GraphView g, SweepArgs a, int32_t idbits,
-                                                      DevCounters* ctr) {
+template <int NA, bool CAP>
+__global__ __launch_bounds__(64) void prune_u8_kernel(GraphView g, SweepArgs a, int32_t idbits) {
   extern __shared__ __align__(16) uint8_t lds[];
   const int lane = threadIdx.x;
   const int64_t p = blockIdx.x;
   const int d = g.d;
   const int stride = u_stride(d);
-  int8_t* U = (int8_t*)lds;                       // U tile (rows 0..63 candidates, 64 = p)
-  int32_t* Stile = (int32_t*)lds;                 // S tile (overlays U after the Gram)
+  int8_t* U = (int8_t*)lds;
+  int32_t* Stile = (int32_t*)lds;  // overlays U once the Gram tile is formed
   const int tile_bytes = max(65 * stride, kSTileBytes);
-  int32_t* nr = (int32_t*)(lds + tile_bytes);     // |u|^2 by rank
-  int32_t* idl = nr + 64;                          // listed ids (slot order), then p
+  int32_t* nr = (int32_t*)(lds + tile_bytes);  // |u|^2 by rank
+  int32_t* idl = nr + 64;                      // listed ids by slot, then p
   const uint8_t* X = (const uint8_t*)g.X;
 
   // ---- a1: read the list -------------------------------------------------
   const int m = g.deg[p];
-  int id = lane < m ? g.nbr[p * g.r_max + lane] : -1;
+  const int id = lane < m ? g.nbr[p * g.r_max + lane] : -1;
   idl[lane] = id;
   if (lane == 0) idl[64] = (int)p;
   __syncthreads();
 
   // ---- a2: coalesced gather into LDS (u = x - 128) -----------------------
-  // Every load of a batch is issued before any of its stores so that the
-  // lane's loads are in flight together.
+  // Every load of a batch is issued before any of its stores.
   {
     const int cpr = d >> 4;  // 16-byte chunks per row
     const int total = 65 * cpr;
@@ -144,7 +163,7 @@ __global__ __launch_bounds__(64) void prune_u8_kernel(GraphView g, SweepArgs a, 
   }
   __syncthreads();
 
-  // ---- a3: p-row S(p, j) and |u_j|^2 ------------------------------------
+  // ---- a3: p-row S(p, j) and |u_j|^2 -------------------------------------
   int32_t nj = 0, dotp = 0, np = 0;
   {
     const int8_t* uj = U + lane * stride;
@@ -176,17 +195,16 @@ __global__ __launch_bounds__(64) void prune_u8_kernel(GraphView g, SweepArgs a, 
                      : kInvalid;
   key = wave_sort(key, lane);
   {
-    uint64_t prev = shfl_u64(key, lane > 0 ? lane - 1 : 0);
-    bool dup = lane > 0 && key != kInvalid && (key >> 6) == (prev >> 6);
-    if (dup) key = kInvalid - 1;  // stays after every valid key; never alive
+    const uint64_t prev = shfl_u64(key, lane > 0 ? lane - 1 : 0);
+    const bool dup = lane > 0 && key != kInvalid && (key >> 6) == (prev >> 6);
+    if (dup) key = kInvalid - 1;  // never alive
   }
   const bool valid = key < kInvalid - 1;
   const uint64_t valid_mask = __ballot(valid);
   const int slot = (int)(key & 63);
   const uint32_t s_rank = valid ? (uint32_t)(key >> shift) : 0u;
   const int id_rank = valid ? (int)((key >> 6) & ((1ull << idbits) - 1)) : -1;
-  const int32_t n_rank = __shfl(nj, slot, 64);
-  nr[lane] = n_rank;
+  nr[lane] = __shfl(nj, slot, 64);
 
   // ---- a5: Gram tile on MFMA (rank order) -------------------------------
   const int l32 = lane & 31;
@@ -206,9 +224,12 @@ __global__ __launch_bounds__(64) void prune_u8_kernel(GraphView g, SweepArgs a, 
     acc01 = __builtin_amdgcn_mfma_i32_32x32x32_i8(f0, f1, acc01, 0, 0, 0);
     acc11 = __builtin_amdgcn_mfma_i32_32x32x32_i8(f1, f1, acc11, 0, 0, 0);
   }
-  __syncthreads();  // every U read done before the S tile overwrites it
+  __syncthreads();  // every U read is done before the S tile overwrites it
 
-  // Accumulator layout of a 32x32 block: lane l holds column l % 32 of rows
+  // S tile, 3072 words: columns 0..31 of rows 0..31 at word 32 i + c;
+  // columns 32..63 of rows 0..63 at word 1024 + 32 i + (c - 32).  Row i of
+  // the tile is then read by lane c at word 32 i + (c % 32) + 1024 (c / 32).
+  // Accumulator layout of a 32 x 32 block: lane l holds column l % 32 of rows
   // 8 (v / 4) + 4 (l / 32) + v % 4 in register v.
   {
     const int32_t ncol0 = nr[l32];
@@ -218,9 +239,9 @@ __global__ __launch_bounds__(64) void prune_u8_kernel(GraphView g, SweepArgs a, 
       const int r = 8 * (v >> 2) + 4 * half + (v & 3);
       const int32_t nrow0 = nr[r];
       const int32_t nrow1 = nr[32 + r];
-      Stile[r * 64 + l32] = nrow0 + ncol0 - 2 * acc00[v];
-      Stile[r * 64 + 32 + l32] = nrow0 + ncol1 - 2 * acc01[v];
-      Stile[32 * 64 + r * 32 + l32] = nrow1 + ncol1 - 2 * acc11[v];
+      Stile[r * 32 + l32] = nrow0 + ncol0 - 2 * acc00[v];
+      Stile[1024 + r * 32 + l32] = nrow0 + ncol1 - 2 * acc01[v];
+      Stile[1024 + (32 + r) * 32 + l32] = nrow1 + ncol1 - 2 * acc11[v];
     }
   }
   __syncthreads();
@@ -230,14 +251,16 @@ __global__ __launch_bounds__(64) void prune_u8_kernel(GraphView g, SweepArgs a, 
 #pragma unroll
   for (int ai = 0; ai < NA; ++ai) T[ai] = alpha_threshold(a.num2[ai], a.den2[ai], s_rank);
 
-  // ---- a7: greedy keep / discard (all alphas in lockstep) ---------------
+  // ---- a7: greedy keep / discard, all alphas in lockstep ----------------
   int rmax[NA];
+  if (CAP) {
 #pragma unroll
-  for (int ai = 0; ai < NA; ++ai) rmax[ai] = 0;
-  for (int o = 0; o < a.n_out; ++o) {
+    for (int ai = 0; ai < NA; ++ai) rmax[ai] = 0;
+    for (int o = 0; o < a.n_out; ++o) {
 #pragma unroll
-    for (int ai = 0; ai < NA; ++ai)
-      if (a.out[o].alpha_idx == ai) rmax[ai] = max(rmax[ai], a.out[o].R);
+      for (int ai = 0; ai < NA; ++ai)
+        if (a.out[o].alpha_idx == ai) rmax[ai] = max(rmax[ai], a.out[o].R);
+    }
   }
   uint64_t alive[NA], kept[NA];
   int cnt[NA];
@@ -247,36 +270,36 @@ __global__ __launch_bounds__(64) void prune_u8_kernel(GraphView g, SweepArgs a, 
     kept[ai] = 0;
     cnt[ai] = 0;
   }
-  // lane offset of the S-row read: rows < 32 span 64 columns, rows >= 32
-  // hold columns 32..63 (lanes < 32 read a duplicate and their bits are
-  // already dead: every rank below p*'s is settled).
-  const int col_hi = 32 * 64 + (lane >= 32 ? lane - 32 : lane);
-  for (;;) {
-    bool any = false;
+  const int lbase = l32 + 1024 * half;
+  while (true) {
     int32_t row[NA];
+    uint64_t any = 0;
 #pragma unroll
     for (int ai = 0; ai < NA; ++ai) {
-      row[ai] = 0;
-      if (alive[ai] != 0 && cnt[ai] < rmax[ai]) {
-        const int i = __ffsll((long long)alive[ai]) - 1;
-        kept[ai] |= 1ull << i;
-        alive[ai] &= ~(1ull << i);
-        ++cnt[ai];
-        if (cnt[ai] < rmax[ai] && alive[ai] != 0) {
-          const int addr = i < 32 ? i * 64 + lane : col_hi + (i - 32) * 32;
-          row[ai] = Stile[addr];
-          any = true;
-        } else {
-          alive[ai] = 0;
-        }
+      // i = lowest surviving rank (s_ff1 gives -1 for an empty mask; clamping
+      // to rank 0 then only re-sets a bit that is already kept, or that the
+      // final mask with the valid ranks removes).
+      int i;
+      asm("s_ff1_i32_b64 %0, %1" : "=s"(i) : "s"(alive[ai]));
+      i = max(i, 0);
+      uint64_t k = kept[ai];
+      asm("s_bitset1_b64 %0, %1" : "+s"(k) : "s"(i));
+      kept[ai] = k;
+      if (CAP) {
+        cnt[ai] += alive[ai] != 0 ? 1 : 0;
+        if (cnt[ai] >= rmax[ai]) alive[ai] = 0;        // stop right after the R-th keep
       }
+      row[ai] = Stile[i * 32 + lbase];
+    }
+#pragma unroll
+    for (int ai = 0; ai < NA; ++ai) {
+      alive[ai] &= ~(uint64_t)__ballot(row[ai] <= T[ai]);  // p* (S = 0) and what it prunes
+      any |= alive[ai];
     }
     if (!any) break;
-#pragma unroll
-    for (int ai = 0; ai < NA; ++ai) {
-      if (alive[ai] != 0) alive[ai] &= ~(uint64_t)__ballot(row[ai] <= T[ai]);
-    }
   }
+#pragma unroll
+  for (int ai = 0; ai < NA; ++ai) kept[ai] &= valid_mask;
 
   // ---- a8: write every output -------------------------------------------
   for (int o = 0; o < a.n_out; ++o) {
@@ -286,8 +309,8 @@ __global__ __launch_bounds__(64) void prune_u8_kernel(GraphView g, SweepArgs a, 
     for (int ai = 0; ai < NA; ++ai)
       if (out.alpha_idx == ai) km = kept[ai];
     const int R = out.R;
-    const int total = __popcll(km);
-    const int cntR = total < R ? total : R;
+    const int tot = __popcll(km);
+    const int cntR = tot < R ? tot : R;
     int32_t* orow = out.nbr + p * R;
     if ((km >> lane) & 1ull) {
       const int pos = __popcll(km & ((1ull << lane) - 1ull));
@@ -296,6 +319,23 @@ __global__ __launch_bounds__(64) void prune_u8_kernel(GraphView g, SweepArgs a, 
     for (int t = cntR + lane; t < R; t += 64) orow[t] = -1;
     if (lane == 0) out.deg[p] = cntR;
   }
+}
+
+template <int NA, bool CAP>
+hipError_t launch_na(const GraphView& g, const SweepArgs& a, int idbits, size_t shmem,
+                     hipStream_t s) {
+  hipLaunchKernelGGL((prune_u8_kernel<NA, CAP>), dim3((unsigned)g.n), dim3(64), shmem, s, g, a,
+                     idbits);
+  return hipGetLastError();
+}
+
+template <int NA>
+hipError_t launch_cap(const GraphView& g, const SweepArgs& a, int idbits, size_t shmem,
+                      hipStream_t s) {
+  bool cap = false;
+  for (int o = 0; o < a.n_out; ++o) cap = cap || a.out[o].R < g.r_max;
+  return cap ? launch_na<NA, true>(g, a, idbits, shmem, s)
+             : launch_na<NA, false>(g, a, idbits, shmem, s);
 }
 
 }  // namespace
@@ -307,29 +347,22 @@ bool prune_u8_supported(const GraphView& g) {
 
 hipError_t launch_prune_u8(const GraphView& g, const SweepArgs& a, DevCounters* ctr,
                            hipStream_t s) {
+  (void)ctr;
   int idbits = 1;
   while ((1ll << idbits) < g.n) ++idbits;
   const int stride = u_stride(g.d);
   const size_t shmem = (size_t)max(65 * stride, kSTileBytes) + (64 + 68) * sizeof(int32_t);
-  dim3 grid((unsigned)g.n), block(64);
-#define RP_LAUNCH_U8(NA_)                                                                   \
-  case NA_:                                                                                 \
-    hipLaunchKernelGGL(prune_u8_kernel<NA_>, grid, block, shmem, s, g, a, idbits, ctr); \
-    break;
   switch (a.n_alpha) {
-    RP_LAUNCH_U8(1)
-    RP_LAUNCH_U8(2)
-    RP_LAUNCH_U8(3)
-    RP_LAUNCH_U8(4)
-    RP_LAUNCH_U8(5)
-    RP_LAUNCH_U8(6)
-    RP_LAUNCH_U8(7)
-    RP_LAUNCH_U8(8)
-    default:
-      return hipErrorInvalidValue;
+    case 1: return launch_cap<1>(g, a, idbits, shmem, s);
+    case 2: return launch_cap<2>(g, a, idbits, shmem, s);
+    case 3: return launch_cap<3>(g, a, idbits, shmem, s);
+    case 4: return launch_cap<4>(g, a, idbits, shmem, s);
+    case 5: return launch_cap<5>(g, a, idbits, shmem, s);
+    case 6: return launch_cap<6>(g, a, idbits, shmem, s);
+    case 7: return launch_cap<7>(g, a, idbits, shmem, s);
+    case 8: return launch_cap<8>(g, a, idbits, shmem, s);
+    default: return hipErrorInvalidValue;
   }
-#undef RP_LAUNCH_U8
-  return hipGetLastError();
 }
 
 }  // namespace rp
