@@ -29,6 +29,8 @@
 //              largest R requested for its alpha; a smaller R is a prefix.
 //  a8  write:  kept ranks are scattered to their positions (popcount of the
 //              kept ranks before them), -1 padded.
+#include <stdlib.h>
+
 #include "dev_common.h"
 
 namespace rp {
@@ -43,6 +45,15 @@ constexpr int kMaxDimU8 = 256;
 constexpr int kGatherBatch = 9;  // 16-byte loads in flight per lane (65 rows x 128 B = 520)
 
 __host__ __device__ constexpr int u_stride(int d) { return d + 16; }
+
+// RP_U8_PERSISTENT=0 selects the one-shot kernel (for timing comparisons).
+bool persistent_enabled() {
+  static const int on = [] {
+    const char* e = getenv("RP_U8_PERSISTENT");
+    return (e && e[0] == '0') ? 0 : 1;
+  }();
+  return on != 0;
+}
 
 // Lane exchange with partner lane ^ J (J a power of two).
 template <int J>
@@ -98,76 +109,67 @@ __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
   return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
 }
 
-// floor(den2 * s / num2) for s < 2^28, exact.
-__device__ __forceinline__ int32_t alpha_threshold(uint32_t num2, uint32_t den2, uint32_t s) {
+// floor(den2 * s / num2) for s < 2^28, exact: s * fl(den2 / num2) is within
+// 2^-24 of the quotient, so one integer correction step settles it.
+__device__ __forceinline__ int32_t alpha_threshold(uint32_t num2, uint32_t den2, double ratio,
+                                                   uint32_t s) {
   const uint64_t B = (uint64_t)den2 * s;
-  int64_t t = (int64_t)((double)B / (double)num2);
-  int64_t r = (int64_t)B - (int64_t)num2 * t;
-  for (int it = 0; it < 4 && r < 0; ++it) { --t; r += num2; }
-  for (int it = 0; it < 4 && r >= (int64_t)num2; ++it) { ++t; r -= num2; }
+  uint32_t t = (uint32_t)((double)s * ratio);
+  const uint64_t nt = (uint64_t)num2 * t;
+  if (nt > B) t -= 1;
+  else if (nt + num2 <= B) t += 1;
   return (int32_t)t;
 }
 
-template <int NA, bool CAP>
-__global__ __launch_bounds__(64) void prune_u8_kernel(GraphView g, SweepArgs a, int32_t idbits) {
-  extern __shared__ __align__(16) uint8_t lds[];
-  const int lane = threadIdx.x;
-  const int64_t p = blockIdx.x;
-  const int d = g.d;
-  const int stride = u_stride(d);
-  int8_t* U = (int8_t*)lds;
-  int32_t* Stile = (int32_t*)lds;  // overlays U once the Gram tile is formed
-  const int tile_bytes = max(65 * stride, kSTileBytes);
-  int32_t* nr = (int32_t*)(lds + tile_bytes);  // |u|^2 by rank
-  int32_t* idl = nr + 64;                      // listed ids by slot, then p
-  const uint8_t* X = (const uint8_t*)g.X;
+// ---------------------------------------------------------------------------
+// Per-vertex pieces shared by the one-shot and the persistent kernels.
+// ---------------------------------------------------------------------------
 
-  // ---- a1: read the list -------------------------------------------------
+struct Tile {
+  int8_t* U;        // candidate rows (slot order) + x_p, as u = x - 128
+  int32_t* S;       // S tile (overlays U after the Gram)
+  int32_t* nr;      // |u|^2 by rank
+  int stride;       // bytes per U row
+};
+
+__device__ __forceinline__ Tile make_tile(uint8_t* lds, int d) {
+  Tile t;
+  t.stride = u_stride(d);
+  t.U = (int8_t*)lds;
+  t.S = (int32_t*)lds;
+  const int tile_bytes = max(65 * t.stride, kSTileBytes);
+  t.nr = (int32_t*)(lds + tile_bytes);
+  return t;
+}
+
+// a1: the list of p (row and degree loads in flight together).
+__device__ __forceinline__ int load_list(const GraphView& g, int64_t p, int lane) {
+  const int raw = lane < g.r_max ? g.nbr[p * g.r_max + lane] : -1;
   const int m = g.deg[p];
-  const int id = lane < m ? g.nbr[p * g.r_max + lane] : -1;
-  idl[lane] = id;
-  if (lane == 0) idl[64] = (int)p;
-  __syncthreads();
+  return lane < m ? raw : -1;
+}
 
-  // ---- a2: coalesced gather into LDS (u = x - 128) -----------------------
-  // Every load of a batch is issued before any of its stores.
-  {
-    const int cpr = d >> 4;  // 16-byte chunks per row
-    const int total = 65 * cpr;
-    const float inv_cpr = 1.0f / (float)cpr;
-    for (int base = 0; base < total; base += 64 * kGatherBatch) {
-      uint4 buf[kGatherBatch];
-      int dst[kGatherBatch];
-#pragma unroll
-      for (int t = 0; t < kGatherBatch; ++t) {
-        const int c = base + lane + 64 * t;
-        buf[t] = make_uint4(0x80808080u, 0x80808080u, 0x80808080u, 0x80808080u);
-        dst[t] = -1;
-        if (c < total) {
-          const int row = (int)(((float)c + 0.5f) * inv_cpr);
-          const int col = c - row * cpr;
-          const int rid = idl[row];
-          dst[t] = row * stride + col * 16;
-          if (rid >= 0) buf[t] = *(const uint4*)(X + (int64_t)rid * d + col * 16);
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < kGatherBatch; ++t) {
-        if (dst[t] >= 0) {
-          uint4 v = buf[t];
-          v.x ^= 0x80808080u; v.y ^= 0x80808080u; v.z ^= 0x80808080u; v.w ^= 0x80808080u;
-          *(uint4*)(U + dst[t]) = v;
-        }
-      }
-    }
-  }
-  __syncthreads();
+// Chunk c of the gather (c = lane + 64 t): row c / cpr (64 = x_p), 16-byte column c % cpr.
+__device__ __forceinline__ void chunk_pos(int c, int cpr, float inv_cpr, int& row, int& col) {
+  row = (int)(((float)c + 0.5f) * inv_cpr);
+  col = c - row * cpr;
+}
 
+struct Front {
+  uint64_t valid_mask;
+  uint32_t s_rank;
+  int id_rank;
+};
+
+// a3 + a4 + a5 on rows already in the U tile: p-row, sort, Gram, S tile.
+__device__ __forceinline__ Front node_front(const Tile& tl, int d, int64_t p, int id, int lane,
+                                            int idbits) {
+  const int stride = tl.stride;
   // ---- a3: p-row S(p, j) and |u_j|^2 -------------------------------------
   int32_t nj = 0, dotp = 0, np = 0;
   {
-    const int8_t* uj = U + lane * stride;
-    const int8_t* up = U + 64 * stride;
+    const int8_t* uj = tl.U + lane * stride;
+    const int8_t* up = tl.U + 64 * stride;
     for (int c = 0; c < d; c += 16) {
       int4 xj = *(const int4*)(uj + c);
       int4 xp = *(const int4*)(up + c);
@@ -193,18 +195,24 @@ __global__ __launch_bounds__(64) void prune_u8_kernel(GraphView g, SweepArgs a, 
   uint64_t key = (id >= 0 && id != (int)p)
                      ? (((uint64_t)sp << shift) | ((uint64_t)(uint32_t)id << 6) | (uint64_t)lane)
                      : kInvalid;
-  key = wave_sort(key, lane);
+  // A list already in (S, id) order -- every RobustPrune output is -- skips
+  // the sorting network.
+  uint64_t prev = shfl_u64(key, lane > 0 ? lane - 1 : 0);
+  if (__ballot(lane > 0 && key < prev)) {
+    key = wave_sort(key, lane);
+    prev = shfl_u64(key, lane > 0 ? lane - 1 : 0);
+  }
   {
-    const uint64_t prev = shfl_u64(key, lane > 0 ? lane - 1 : 0);
     const bool dup = lane > 0 && key != kInvalid && (key >> 6) == (prev >> 6);
     if (dup) key = kInvalid - 1;  // never alive
   }
   const bool valid = key < kInvalid - 1;
-  const uint64_t valid_mask = __ballot(valid);
+  Front f;
+  f.valid_mask = __ballot(valid);
   const int slot = (int)(key & 63);
-  const uint32_t s_rank = valid ? (uint32_t)(key >> shift) : 0u;
-  const int id_rank = valid ? (int)((key >> 6) & ((1ull << idbits) - 1)) : -1;
-  nr[lane] = __shfl(nj, slot, 64);
+  f.s_rank = valid ? (uint32_t)(key >> shift) : 0u;
+  f.id_rank = valid ? (int)((key >> 6) & ((1ull << idbits) - 1)) : -1;
+  tl.nr[lane] = __shfl(nj, slot, 64);
 
   // ---- a5: Gram tile on MFMA (rank order) -------------------------------
   const int l32 = lane & 31;
@@ -217,8 +225,8 @@ __global__ __launch_bounds__(64) void prune_u8_kernel(GraphView g, SweepArgs a, 
     const int off = kk + half * 16;
     v4i f0 = {0, 0, 0, 0}, f1 = {0, 0, 0, 0};
     if (off < d) {
-      f0 = *(const v4i*)(U + sl0 * stride + off);
-      f1 = *(const v4i*)(U + sl1 * stride + off);
+      f0 = *(const v4i*)(tl.U + sl0 * stride + off);
+      f1 = *(const v4i*)(tl.U + sl1 * stride + off);
     }
     acc00 = __builtin_amdgcn_mfma_i32_32x32x32_i8(f0, f0, acc00, 0, 0, 0);
     acc01 = __builtin_amdgcn_mfma_i32_32x32x32_i8(f0, f1, acc01, 0, 0, 0);
@@ -232,24 +240,30 @@ __global__ __launch_bounds__(64) void prune_u8_kernel(GraphView g, SweepArgs a, 
   // Accumulator layout of a 32 x 32 block: lane l holds column l % 32 of rows
   // 8 (v / 4) + 4 (l / 32) + v % 4 in register v.
   {
-    const int32_t ncol0 = nr[l32];
-    const int32_t ncol1 = nr[32 + l32];
+    const int32_t ncol0 = tl.nr[l32];
+    const int32_t ncol1 = tl.nr[32 + l32];
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int r = 8 * (v >> 2) + 4 * half + (v & 3);
-      const int32_t nrow0 = nr[r];
-      const int32_t nrow1 = nr[32 + r];
-      Stile[r * 32 + l32] = nrow0 + ncol0 - 2 * acc00[v];
-      Stile[1024 + r * 32 + l32] = nrow0 + ncol1 - 2 * acc01[v];
-      Stile[1024 + (32 + r) * 32 + l32] = nrow1 + ncol1 - 2 * acc11[v];
+      const int32_t nrow0 = tl.nr[r];
+      const int32_t nrow1 = tl.nr[32 + r];
+      tl.S[r * 32 + l32] = nrow0 + ncol0 - 2 * acc00[v];
+      tl.S[1024 + r * 32 + l32] = nrow0 + ncol1 - 2 * acc01[v];
+      tl.S[1024 + (32 + r) * 32 + l32] = nrow1 + ncol1 - 2 * acc11[v];
     }
   }
-  __syncthreads();
+  return f;
+}
 
+// a6 + a7 + a8 on the S tile: thresholds, greedy, outputs of p.
+template <int NA, bool CAP>
+__device__ __forceinline__ void node_back(const Tile& tl, const SweepArgs& a, int64_t p,
+                                          const Front& f, int lane) {
   // ---- a6: thresholds per alpha -----------------------------------------
   int32_t T[NA];
 #pragma unroll
-  for (int ai = 0; ai < NA; ++ai) T[ai] = alpha_threshold(a.num2[ai], a.den2[ai], s_rank);
+  for (int ai = 0; ai < NA; ++ai)
+    T[ai] = alpha_threshold(a.num2[ai], a.den2[ai], a.ratio[ai], f.s_rank);
 
   // ---- a7: greedy keep / discard, all alphas in lockstep ----------------
   int rmax[NA];
@@ -266,11 +280,11 @@ __global__ __launch_bounds__(64) void prune_u8_kernel(GraphView g, SweepArgs a, 
   int cnt[NA];
 #pragma unroll
   for (int ai = 0; ai < NA; ++ai) {
-    alive[ai] = valid_mask;
+    alive[ai] = f.valid_mask;
     kept[ai] = 0;
     cnt[ai] = 0;
   }
-  const int lbase = l32 + 1024 * half;
+  const int lbase = (lane & 31) + 1024 * (lane >> 5);
   while (true) {
     int32_t row[NA];
     uint64_t any = 0;
@@ -289,7 +303,7 @@ __global__ __launch_bounds__(64) void prune_u8_kernel(GraphView g, SweepArgs a, 
         cnt[ai] += alive[ai] != 0 ? 1 : 0;
         if (cnt[ai] >= rmax[ai]) alive[ai] = 0;        // stop right after the R-th keep
       }
-      row[ai] = Stile[i * 32 + lbase];
+      row[ai] = tl.S[i * 32 + lbase];
     }
 #pragma unroll
     for (int ai = 0; ai < NA; ++ai) {
@@ -299,7 +313,7 @@ __global__ __launch_bounds__(64) void prune_u8_kernel(GraphView g, SweepArgs a, 
     if (!any) break;
   }
 #pragma unroll
-  for (int ai = 0; ai < NA; ++ai) kept[ai] &= valid_mask;
+  for (int ai = 0; ai < NA; ++ai) kept[ai] &= f.valid_mask;
 
   // ---- a8: write every output -------------------------------------------
   for (int o = 0; o < a.n_out; ++o) {
@@ -314,16 +328,148 @@ __global__ __launch_bounds__(64) void prune_u8_kernel(GraphView g, SweepArgs a, 
     int32_t* orow = out.nbr + p * R;
     if ((km >> lane) & 1ull) {
       const int pos = __popcll(km & ((1ull << lane) - 1ull));
-      if (pos < R) orow[pos] = id_rank;
+      if (pos < R) orow[pos] = f.id_rank;
     }
     for (int t = cntR + lane; t < R; t += 64) orow[t] = -1;
     if (lane == 0) out.deg[p] = cntR;
   }
 }
 
+// One wavefront per vertex (any d multiple of 16 up to 256).
+template <int NA, bool CAP>
+__global__ __launch_bounds__(64) void prune_u8_kernel(GraphView g, SweepArgs a, int32_t idbits) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  const int lane = threadIdx.x;
+  const int64_t p = blockIdx.x;
+  const int d = g.d;
+  const Tile tl = make_tile(lds, d);
+  int32_t* idl = tl.nr + 64;  // listed ids by slot, then p
+  const uint8_t* X = (const uint8_t*)g.X;
+
+  const int id = load_list(g, p, lane);
+  idl[lane] = id;
+  if (lane == 0) idl[64] = (int)p;
+  __syncthreads();
+
+  // ---- a2: coalesced gather into LDS (u = x - 128) -----------------------
+  // Every load of a batch is issued before any of its stores.
+  {
+    const int cpr = d >> 4;
+    const int total = 65 * cpr;
+    const float inv_cpr = 1.0f / (float)cpr;
+    for (int base = 0; base < total; base += 64 * kGatherBatch) {
+      uint4 buf[kGatherBatch];
+      int dst[kGatherBatch];
+#pragma unroll
+      for (int t = 0; t < kGatherBatch; ++t) {
+        const int c = base + lane + 64 * t;
+        buf[t] = make_uint4(0x80808080u, 0x80808080u, 0x80808080u, 0x80808080u);
+        dst[t] = -1;
+        if (c < total) {
+          int row, col;
+          chunk_pos(c, cpr, inv_cpr, row, col);
+          const int rid = idl[row];
+          dst[t] = row * tl.stride + col * 16;
+          if (rid >= 0) buf[t] = *(const uint4*)(X + (int64_t)rid * d + col * 16);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < kGatherBatch; ++t) {
+        if (dst[t] >= 0) {
+          uint4 v = buf[t];
+          v.x ^= 0x80808080u; v.y ^= 0x80808080u; v.z ^= 0x80808080u; v.w ^= 0x80808080u;
+          *(uint4*)(tl.U + dst[t]) = v;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const Front f = node_front(tl, d, p, id, lane, idbits);
+  __syncthreads();
+  node_back<NA, CAP>(tl, a, p, f, lane);
+}
+
+// Persistent form for d <= 128 (at most 9 chunks per lane): wavefront w walks
+// vertices w, w + G, ... and keeps the next vertex's rows in registers while
+// it prunes the current one.
+template <int NA, bool CAP>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3)))
+void prune_u8_persistent(GraphView g, SweepArgs a, int32_t idbits) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  const int lane = threadIdx.x;
+  const int d = g.d;
+  const Tile tl = make_tile(lds, d);
+  const uint8_t* X = (const uint8_t*)g.X;
+  const int cpr = d >> 4;
+  const int total = 65 * cpr;
+  const float inv_cpr = 1.0f / (float)cpr;
+  const int64_t step = gridDim.x;
+  int64_t p = blockIdx.x;
+  if (p >= g.n) return;
+
+  uint4 buf[kGatherBatch];
+  // rows of vertex v with list vid: issue every load of this lane
+  auto issue_rows = [&](int64_t v, int vid, int ln) {
+#pragma unroll
+    for (int t = 0; t < kGatherBatch; ++t) {
+      const int c = ln + 64 * t;
+      buf[t] = make_uint4(0x80808080u, 0x80808080u, 0x80808080u, 0x80808080u);
+      int row, col;
+      chunk_pos(c, cpr, inv_cpr, row, col);
+      int rid = __shfl(vid, row < 64 ? row : 0, 64);
+      if (row >= 64) rid = (int)v;
+      if (c < total && rid >= 0) buf[t] = *(const uint4*)(X + (int64_t)rid * d + col * 16);
+    }
+  };
+  int id = load_list(g, p, lane);
+  issue_rows(p, id, lane);
+
+  for (;;) {
+    // An opaque copy of the lane index per vertex keeps lane-derived address
+    // arithmetic inside the loop instead of holding it in registers across it.
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+    __syncthreads();  // the previous vertex's greedy is done with the S tile
+#pragma unroll
+    for (int t = 0; t < kGatherBatch; ++t) {
+      const int c = ln + 64 * t;
+      if (c < total) {
+        int row, col;
+        chunk_pos(c, cpr, inv_cpr, row, col);
+        uint4 v = buf[t];
+        v.x ^= 0x80808080u; v.y ^= 0x80808080u; v.z ^= 0x80808080u; v.w ^= 0x80808080u;
+        *(uint4*)(tl.U + row * tl.stride + col * 16) = v;
+      }
+    }
+    const int64_t q = p + step;
+    const int id_next = q < g.n ? load_list(g, q, ln) : -1;  // in flight meanwhile
+    __syncthreads();
+    const Front f = node_front(tl, d, p, id, ln, idbits);
+    if (q < g.n) issue_rows(q, id_next, ln);  // in flight during the greedy
+    __syncthreads();
+    node_back<NA, CAP>(tl, a, p, f, ln);
+    if (q >= g.n) break;
+    p = q;
+    id = id_next;
+  }
+}
+
 template <int NA, bool CAP>
 hipError_t launch_na(const GraphView& g, const SweepArgs& a, int idbits, size_t shmem,
                      hipStream_t s) {
+  if (g.d <= 128 && persistent_enabled()) {
+    auto kern = prune_u8_persistent<NA, CAP>;
+    int dev = 0, ncu = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return hipErrorInvalidDevice;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, shmem) != hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    const int64_t blocks = std::min<int64_t>(g.n, (int64_t)per_cu * ncu);
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64), shmem, s, g, a, idbits);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL((prune_u8_kernel<NA, CAP>), dim3((unsigned)g.n), dim3(64), shmem, s, g, a,
                      idbits);
   return hipGetLastError();

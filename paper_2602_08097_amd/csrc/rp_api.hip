@@ -209,6 +209,7 @@ rp_status rp_prune_sweep(rp_graph_t g, const rp_alpha* alphas, int32_t n_a, cons
     if (st != RP_OK) return st;
     a.num2[i] = (uint32_t)alphas[i].num * alphas[i].num;
     a.den2[i] = (uint32_t)alphas[i].den * alphas[i].den;
+    a.ratio[i] = (double)a.den2[i] / (double)a.num2[i];
   }
   for (int ia = 0; ia < n_a; ++ia)
     for (int ir = 0; ir < n_R; ++ir) {

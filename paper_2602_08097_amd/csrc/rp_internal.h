@@ -33,6 +33,7 @@ struct SweepOut {
 struct SweepArgs {
   uint32_t num2[kMaxAlphas];
   uint32_t den2[kMaxAlphas];
+  double ratio[kMaxAlphas];  // den^2 / num^2 rounded to FP64 (a first guess only)
   int32_t n_alpha;
   int32_t n_out;
   SweepOut out[kMaxOutputs];
