@@ -29,8 +29,6 @@
 //              largest R requested for its alpha; a smaller R is a prefix.
 //  a8  write:  kept ranks are scattered to their positions (popcount of the
 //              kept ranks before them), -1 padded.
-#include <stdlib.h>
-
 #include "dev_common.h"
 
 namespace rp {
@@ -40,20 +38,12 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 
 namespace {
 
-constexpr int kSTileBytes = 3072 * 4;  // S tile, 12 KiB: the blocks on and above the diagonal
+constexpr int kSTileBytes = 3072;  // count tile, 3 KiB: the blocks on and above the diagonal
 constexpr int kMaxDimU8 = 256;
 constexpr int kGatherBatch = 9;  // 16-byte loads in flight per lane (65 rows x 128 B = 520)
 
 __host__ __device__ constexpr int u_stride(int d) { return d + 16; }
 
-// RP_U8_PERSISTENT=0 selects the one-shot kernel (for timing comparisons).
-bool persistent_enabled() {
-  static const int on = [] {
-    const char* e = getenv("RP_U8_PERSISTENT");
-    return (e && e[0] == '0') ? 0 : 1;
-  }();
-  return on != 0;
-}
 
 // Lane exchange with partner lane ^ J (J a power of two).
 template <int J>
@@ -122,12 +112,12 @@ __device__ __forceinline__ int32_t alpha_threshold(uint32_t num2, uint32_t den2,
 }
 
 // ---------------------------------------------------------------------------
-// Per-vertex pieces shared by the one-shot and the persistent kernels.
+// Per-vertex pieces of the kernel.
 // ---------------------------------------------------------------------------
 
 struct Tile {
   int8_t* U;        // candidate rows (slot order) + x_p, as u = x - 128
-  int32_t* S;       // S tile (overlays U after the Gram)
+  uint8_t* C;       // count tile (overlays U after the Gram)
   int32_t* nr;      // |u|^2 by rank
   int stride;       // bytes per U row
 };
@@ -136,7 +126,7 @@ __device__ __forceinline__ Tile make_tile(uint8_t* lds, int d) {
   Tile t;
   t.stride = u_stride(d);
   t.U = (int8_t*)lds;
-  t.S = (int32_t*)lds;
+  t.C = lds;
   const int tile_bytes = max(65 * t.stride, kSTileBytes);
   t.nr = (int32_t*)(lds + tile_bytes);
   return t;
@@ -157,13 +147,17 @@ __device__ __forceinline__ void chunk_pos(int c, int cpr, float inv_cpr, int& ro
 
 struct Front {
   uint64_t valid_mask;
-  uint32_t s_rank;
   int id_rank;
 };
 
-// a3 + a4 + a5 on rows already in the U tile: p-row, sort, Gram, S tile.
-__device__ __forceinline__ Front node_front(const Tile& tl, int d, int64_t p, int id, int lane,
-                                            int idbits) {
+// a3..a6 on rows already in the U tile: p-row, sort, Gram, thresholds and the
+// count tile.  Alphas arrive in ascending order, so their thresholds
+// T_0(j) >= T_1(j) >= ... and the alphas whose test holds for a pair (i, j)
+// are a prefix 0..c-1; the tile stores c(i, j) = #{k : S(i, j) <= T_k(j)} and
+// chain k prunes j from i exactly when c(i, j) > k.
+template <int NA>
+__device__ __forceinline__ Front node_front(const Tile& tl, const SweepArgs& a, int d, int64_t p,
+                                            int id, int lane, int idbits) {
   const int stride = tl.stride;
   // ---- a3: p-row S(p, j) and |u_j|^2 -------------------------------------
   int32_t nj = 0, dotp = 0, np = 0;
@@ -210,13 +204,22 @@ __device__ __forceinline__ Front node_front(const Tile& tl, int d, int64_t p, in
   Front f;
   f.valid_mask = __ballot(valid);
   const int slot = (int)(key & 63);
-  f.s_rank = valid ? (uint32_t)(key >> shift) : 0u;
+  const uint32_t s_rank = valid ? (uint32_t)(key >> shift) : 0u;
   f.id_rank = valid ? (int)((key >> 6) & ((1ull << idbits) - 1)) : -1;
   tl.nr[lane] = __shfl(nj, slot, 64);
 
-  // ---- a5: Gram tile on MFMA (rank order) -------------------------------
+  // ---- a6: thresholds of this rank, then of the lane's two tile columns ---
   const int l32 = lane & 31;
   const int half = lane >> 5;
+  int32_t T0[NA], T1[NA];
+#pragma unroll
+  for (int k = 0; k < NA; ++k) {
+    const int32_t t = alpha_threshold(a.num2[k], a.den2[k], a.ratio[k], s_rank);
+    T0[k] = __shfl(t, l32, 64);        // column l32
+    T1[k] = __shfl(t, 32 + l32, 64);   // column 32 + l32
+  }
+
+  // ---- a5: Gram tile on MFMA (rank order) -------------------------------
   const int sl0 = __shfl(slot, l32, 64);        // row of rank l32
   const int sl1 = __shfl(slot, 32 + l32, 64);   // row of rank 32 + l32
   v16i acc00 = {0}, acc01 = {0}, acc11 = {0};
@@ -232,11 +235,11 @@ __device__ __forceinline__ Front node_front(const Tile& tl, int d, int64_t p, in
     acc01 = __builtin_amdgcn_mfma_i32_32x32x32_i8(f0, f1, acc01, 0, 0, 0);
     acc11 = __builtin_amdgcn_mfma_i32_32x32x32_i8(f1, f1, acc11, 0, 0, 0);
   }
-  __syncthreads();  // every U read is done before the S tile overwrites it
+  __syncthreads();  // every U read is done before the count tile overwrites it
 
-  // S tile, 3072 words: columns 0..31 of rows 0..31 at word 32 i + c;
-  // columns 32..63 of rows 0..63 at word 1024 + 32 i + (c - 32).  Row i of
-  // the tile is then read by lane c at word 32 i + (c % 32) + 1024 (c / 32).
+  // Count tile, 3072 bytes: columns 0..31 of rows 0..31 at byte 32 i + c;
+  // columns 32..63 of rows 0..63 at byte 1024 + 32 i + (c - 32).  Row i is
+  // then read by lane c at byte 32 i + (c % 32) + 1024 (c / 32).
   // Accumulator layout of a 32 x 32 block: lane l holds column l % 32 of rows
   // 8 (v / 4) + 4 (l / 32) + v % 4 in register v.
   {
@@ -247,24 +250,28 @@ __device__ __forceinline__ Front node_front(const Tile& tl, int d, int64_t p, in
       const int r = 8 * (v >> 2) + 4 * half + (v & 3);
       const int32_t nrow0 = tl.nr[r];
       const int32_t nrow1 = tl.nr[32 + r];
-      tl.S[r * 32 + l32] = nrow0 + ncol0 - 2 * acc00[v];
-      tl.S[1024 + r * 32 + l32] = nrow0 + ncol1 - 2 * acc01[v];
-      tl.S[1024 + (32 + r) * 32 + l32] = nrow1 + ncol1 - 2 * acc11[v];
+      const int32_t s00 = nrow0 + ncol0 - 2 * acc00[v];
+      const int32_t s01 = nrow0 + ncol1 - 2 * acc01[v];
+      const int32_t s11 = nrow1 + ncol1 - 2 * acc11[v];
+      uint32_t c00 = 0, c01 = 0, c11 = 0;
+#pragma unroll
+      for (int k = 0; k < NA; ++k) {
+        c00 += s00 <= T0[k] ? 1u : 0u;
+        c01 += s01 <= T1[k] ? 1u : 0u;
+        c11 += s11 <= T1[k] ? 1u : 0u;
+      }
+      tl.C[r * 32 + l32] = (uint8_t)c00;
+      tl.C[1024 + r * 32 + l32] = (uint8_t)c01;
+      tl.C[1024 + (32 + r) * 32 + l32] = (uint8_t)c11;
     }
   }
   return f;
 }
 
-// a6 + a7 + a8 on the S tile: thresholds, greedy, outputs of p.
+// a7 + a8 on the count tile: greedy, outputs of p.
 template <int NA, bool CAP>
 __device__ __forceinline__ void node_back(const Tile& tl, const SweepArgs& a, int64_t p,
                                           const Front& f, int lane) {
-  // ---- a6: thresholds per alpha -----------------------------------------
-  int32_t T[NA];
-#pragma unroll
-  for (int ai = 0; ai < NA; ++ai)
-    T[ai] = alpha_threshold(a.num2[ai], a.den2[ai], a.ratio[ai], f.s_rank);
-
   // ---- a7: greedy keep / discard, all alphas in lockstep ----------------
   int rmax[NA];
   if (CAP) {
@@ -286,7 +293,7 @@ __device__ __forceinline__ void node_back(const Tile& tl, const SweepArgs& a, in
   }
   const int lbase = (lane & 31) + 1024 * (lane >> 5);
   while (true) {
-    int32_t row[NA];
+    uint32_t row[NA];
     uint64_t any = 0;
 #pragma unroll
     for (int ai = 0; ai < NA; ++ai) {
@@ -303,11 +310,12 @@ __device__ __forceinline__ void node_back(const Tile& tl, const SweepArgs& a, in
         cnt[ai] += alive[ai] != 0 ? 1 : 0;
         if (cnt[ai] >= rmax[ai]) alive[ai] = 0;        // stop right after the R-th keep
       }
-      row[ai] = tl.S[i * 32 + lbase];
+      row[ai] = tl.C[i * 32 + lbase];
     }
 #pragma unroll
     for (int ai = 0; ai < NA; ++ai) {
-      alive[ai] &= ~(uint64_t)__ballot(row[ai] <= T[ai]);  // p* (S = 0) and what it prunes
+      // p* itself (S = 0 passes every threshold) and what it prunes
+      alive[ai] &= ~(uint64_t)__ballot(row[ai] > (uint32_t)ai);
       any |= alive[ai];
     }
     if (!any) break;
@@ -384,92 +392,14 @@ __global__ __launch_bounds__(64) void prune_u8_kernel(GraphView g, SweepArgs a, 
     }
   }
   __syncthreads();
-  const Front f = node_front(tl, d, p, id, lane, idbits);
+  const Front f = node_front<NA>(tl, a, d, p, id, lane, idbits);
   __syncthreads();
   node_back<NA, CAP>(tl, a, p, f, lane);
-}
-
-// Persistent form for d <= 128 (at most 9 chunks per lane): wavefront w walks
-// vertices w, w + G, ... and keeps the next vertex's rows in registers while
-// it prunes the current one.
-template <int NA, bool CAP>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3)))
-void prune_u8_persistent(GraphView g, SweepArgs a, int32_t idbits) {
-  extern __shared__ __align__(16) uint8_t lds[];
-  const int lane = threadIdx.x;
-  const int d = g.d;
-  const Tile tl = make_tile(lds, d);
-  const uint8_t* X = (const uint8_t*)g.X;
-  const int cpr = d >> 4;
-  const int total = 65 * cpr;
-  const float inv_cpr = 1.0f / (float)cpr;
-  const int64_t step = gridDim.x;
-  int64_t p = blockIdx.x;
-  if (p >= g.n) return;
-
-  uint4 buf[kGatherBatch];
-  // rows of vertex v with list vid: issue every load of this lane
-  auto issue_rows = [&](int64_t v, int vid, int ln) {
-#pragma unroll
-    for (int t = 0; t < kGatherBatch; ++t) {
-      const int c = ln + 64 * t;
-      buf[t] = make_uint4(0x80808080u, 0x80808080u, 0x80808080u, 0x80808080u);
-      int row, col;
-      chunk_pos(c, cpr, inv_cpr, row, col);
-      int rid = __shfl(vid, row < 64 ? row : 0, 64);
-      if (row >= 64) rid = (int)v;
-      if (c < total && rid >= 0) buf[t] = *(const uint4*)(X + (int64_t)rid * d + col * 16);
-    }
-  };
-  int id = load_list(g, p, lane);
-  issue_rows(p, id, lane);
-
-  for (;;) {
-    // An opaque copy of the lane index per vertex keeps lane-derived address
-    // arithmetic inside the loop instead of holding it in registers across it.
-    int ln = lane;
-    asm volatile("" : "+v"(ln));
-    __syncthreads();  // the previous vertex's greedy is done with the S tile
-#pragma unroll
-    for (int t = 0; t < kGatherBatch; ++t) {
-      const int c = ln + 64 * t;
-      if (c < total) {
-        int row, col;
-        chunk_pos(c, cpr, inv_cpr, row, col);
-        uint4 v = buf[t];
-        v.x ^= 0x80808080u; v.y ^= 0x80808080u; v.z ^= 0x80808080u; v.w ^= 0x80808080u;
-        *(uint4*)(tl.U + row * tl.stride + col * 16) = v;
-      }
-    }
-    const int64_t q = p + step;
-    const int id_next = q < g.n ? load_list(g, q, ln) : -1;  // in flight meanwhile
-    __syncthreads();
-    const Front f = node_front(tl, d, p, id, ln, idbits);
-    if (q < g.n) issue_rows(q, id_next, ln);  // in flight during the greedy
-    __syncthreads();
-    node_back<NA, CAP>(tl, a, p, f, ln);
-    if (q >= g.n) break;
-    p = q;
-    id = id_next;
-  }
 }
 
 template <int NA, bool CAP>
 hipError_t launch_na(const GraphView& g, const SweepArgs& a, int idbits, size_t shmem,
                      hipStream_t s) {
-  if (g.d <= 128 && persistent_enabled()) {
-    auto kern = prune_u8_persistent<NA, CAP>;
-    int dev = 0, ncu = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      return hipErrorInvalidDevice;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, shmem) != hipSuccess ||
-        per_cu < 1)
-      per_cu = 1;
-    const int64_t blocks = std::min<int64_t>(g.n, (int64_t)per_cu * ncu);
-    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64), shmem, s, g, a, idbits);
-    return hipGetLastError();
-  }
   hipLaunchKernelGGL((prune_u8_kernel<NA, CAP>), dim3((unsigned)g.n), dim3(64), shmem, s, g, a,
                      idbits);
   return hipGetLastError();
@@ -491,9 +421,31 @@ bool prune_u8_supported(const GraphView& g) {
          g.n <= (1ll << 30);
 }
 
-hipError_t launch_prune_u8(const GraphView& g, const SweepArgs& a, DevCounters* ctr,
+hipError_t launch_prune_u8(const GraphView& g, const SweepArgs& a_in, DevCounters* ctr,
                            hipStream_t s) {
   (void)ctr;
+  // the kernel takes the alphas in ascending order (num_a den_b vs num_b den_a)
+  SweepArgs a = a_in;
+  int order[kMaxAlphas];
+  for (int i = 0; i < a_in.n_alpha; ++i) order[i] = i;
+  for (int i = 1; i < a_in.n_alpha; ++i) {
+    int v = order[i], j = i - 1;
+    // compare alpha_v < alpha_order[j] on squares: num2_v den2_o < num2_o den2_v
+    while (j >= 0 && (uint64_t)a_in.num2[v] * a_in.den2[order[j]] <
+                         (uint64_t)a_in.num2[order[j]] * a_in.den2[v]) {
+      order[j + 1] = order[j];
+      --j;
+    }
+    order[j + 1] = v;
+  }
+  int rank_of[kMaxAlphas];
+  for (int k = 0; k < a_in.n_alpha; ++k) {
+    a.num2[k] = a_in.num2[order[k]];
+    a.den2[k] = a_in.den2[order[k]];
+    a.ratio[k] = a_in.ratio[order[k]];
+    rank_of[order[k]] = k;
+  }
+  for (int o = 0; o < a_in.n_out; ++o) a.out[o].alpha_idx = rank_of[a_in.out[o].alpha_idx];
   int idbits = 1;
   while ((1ll << idbits) < g.n) ++idbits;
   const int stride = u_stride(g.d);
