@@ -93,6 +93,13 @@ __device__ __forceinline__ uint64_t wave_sort(uint64_t k, int lane) {
   return k;
 }
 
+// A wave-uniform 64-bit value pinned to scalar registers.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
   int lo = __shfl((int)(uint32_t)v, src, 64);
   int hi = __shfl((int)(uint32_t)(v >> 32), src, 64);
@@ -256,10 +263,11 @@ __device__ __forceinline__ Front node_front(const Tile& tl, const SweepArgs& a, 
       uint32_t c00 = 0, c01 = 0, c11 = 0;
 #pragma unroll
       for (int k = 0; k < NA; ++k) {
-        c00 += s00 <= T0[k] ? 1u : 0u;
-        c01 += s01 <= T1[k] ? 1u : 0u;
-        c11 += s11 <= T1[k] ? 1u : 0u;
+        c00 += (uint32_t)(s00 <= T0[k]);
+        c01 += (uint32_t)(s01 <= T1[k]);
+        c11 += (uint32_t)(s11 <= T1[k]);
       }
+      asm("" : "+v"(c00), "+v"(c01), "+v"(c11));  // keep the counts 32-bit (carry adds)
       tl.C[r * 32 + l32] = (uint8_t)c00;
       tl.C[1024 + r * 32 + l32] = (uint8_t)c01;
       tl.C[1024 + (32 + r) * 32 + l32] = (uint8_t)c11;
@@ -269,18 +277,18 @@ __device__ __forceinline__ Front node_front(const Tile& tl, const SweepArgs& a, 
 }
 
 // a7 + a8 on the count tile: greedy, outputs of p.
-template <int NA, bool CAP>
+template <int NA, int NR, bool CAP>
 __device__ __forceinline__ void node_back(const Tile& tl, const SweepArgs& a, int64_t p,
                                           const Front& f, int lane) {
   // ---- a7: greedy keep / discard, all alphas in lockstep ----------------
+  // outputs are alpha-major: output ai * NR + ir has alpha ai, bound R_ir
   int rmax[NA];
   if (CAP) {
 #pragma unroll
-    for (int ai = 0; ai < NA; ++ai) rmax[ai] = 0;
-    for (int o = 0; o < a.n_out; ++o) {
+    for (int ai = 0; ai < NA; ++ai) {
+      rmax[ai] = 0;
 #pragma unroll
-      for (int ai = 0; ai < NA; ++ai)
-        if (a.out[o].alpha_idx == ai) rmax[ai] = max(rmax[ai], a.out[o].R);
+      for (int ir = 0; ir < NR; ++ir) rmax[ai] = max(rmax[ai], a.out[ai * NR + ir].R);
     }
   }
   uint64_t alive[NA], kept[NA];
@@ -300,10 +308,11 @@ __device__ __forceinline__ void node_back(const Tile& tl, const SweepArgs& a, in
       // i = lowest surviving rank (s_ff1 gives -1 for an empty mask; clamping
       // to rank 0 then only re-sets a bit that is already kept, or that the
       // final mask with the valid ranks removes).
+      const uint64_t al = uniform_u64(alive[ai]);
       int i;
-      asm("s_ff1_i32_b64 %0, %1" : "=s"(i) : "s"(alive[ai]));
+      asm("s_ff1_i32_b64 %0, %1" : "=s"(i) : "s"(al));
       i = max(i, 0);
-      uint64_t k = kept[ai];
+      uint64_t k = uniform_u64(kept[ai]);
       asm("s_bitset1_b64 %0, %1" : "+s"(k) : "s"(i));
       kept[ai] = k;
       if (CAP) {
@@ -324,27 +333,27 @@ __device__ __forceinline__ void node_back(const Tile& tl, const SweepArgs& a, in
   for (int ai = 0; ai < NA; ++ai) kept[ai] &= f.valid_mask;
 
   // ---- a8: write every output -------------------------------------------
-  for (int o = 0; o < a.n_out; ++o) {
-    const SweepOut& out = a.out[o];
-    uint64_t km = 0;
 #pragma unroll
-    for (int ai = 0; ai < NA; ++ai)
-      if (out.alpha_idx == ai) km = kept[ai];
-    const int R = out.R;
+  for (int ai = 0; ai < NA; ++ai) {
+    const uint64_t km = kept[ai];
     const int tot = __popcll(km);
-    const int cntR = tot < R ? tot : R;
-    int32_t* orow = out.nbr + p * R;
-    if ((km >> lane) & 1ull) {
-      const int pos = __popcll(km & ((1ull << lane) - 1ull));
-      if (pos < R) orow[pos] = f.id_rank;
+    const bool mine = (km >> lane) & 1ull;
+    const int pos = __popcll(km & ((1ull << lane) - 1ull));
+#pragma unroll
+    for (int ir = 0; ir < NR; ++ir) {
+      const SweepOut& out = a.out[ai * NR + ir];
+      const int R = out.R;
+      const int cntR = tot < R ? tot : R;
+      int32_t* orow = out.nbr + p * R;
+      if (mine && pos < R) orow[pos] = f.id_rank;
+      for (int t = cntR + lane; t < R; t += 64) orow[t] = -1;
+      if (lane == 0) out.deg[p] = cntR;
     }
-    for (int t = cntR + lane; t < R; t += 64) orow[t] = -1;
-    if (lane == 0) out.deg[p] = cntR;
   }
 }
 
 // One wavefront per vertex (any d multiple of 16 up to 256).
-template <int NA, bool CAP>
+template <int NA, int NR, bool CAP>
 __global__ __launch_bounds__(64) void prune_u8_kernel(GraphView g, SweepArgs a, int32_t idbits) {
   extern __shared__ __align__(16) uint8_t lds[];
   const int lane = threadIdx.x;
@@ -394,24 +403,33 @@ __global__ __launch_bounds__(64) void prune_u8_kernel(GraphView g, SweepArgs a, 
   __syncthreads();
   const Front f = node_front<NA>(tl, a, d, p, id, lane, idbits);
   __syncthreads();
-  node_back<NA, CAP>(tl, a, p, f, lane);
+  node_back<NA, NR, CAP>(tl, a, p, f, lane);
 }
 
-template <int NA, bool CAP>
-hipError_t launch_na(const GraphView& g, const SweepArgs& a, int idbits, size_t shmem,
+template <int NA, int NR>
+hipError_t launch_nr(const GraphView& g, const SweepArgs& a, int idbits, size_t shmem,
                      hipStream_t s) {
-  hipLaunchKernelGGL((prune_u8_kernel<NA, CAP>), dim3((unsigned)g.n), dim3(64), shmem, s, g, a,
-                     idbits);
+  bool cap = false;
+  for (int o = 0; o < a.n_out; ++o) cap = cap || a.out[o].R < g.r_max;
+  if (cap)
+    hipLaunchKernelGGL((prune_u8_kernel<NA, NR, true>), dim3((unsigned)g.n), dim3(64), shmem, s,
+                       g, a, idbits);
+  else
+    hipLaunchKernelGGL((prune_u8_kernel<NA, NR, false>), dim3((unsigned)g.n), dim3(64), shmem,
+                       s, g, a, idbits);
   return hipGetLastError();
 }
 
 template <int NA>
-hipError_t launch_cap(const GraphView& g, const SweepArgs& a, int idbits, size_t shmem,
-                      hipStream_t s) {
-  bool cap = false;
-  for (int o = 0; o < a.n_out; ++o) cap = cap || a.out[o].R < g.r_max;
-  return cap ? launch_na<NA, true>(g, a, idbits, shmem, s)
-             : launch_na<NA, false>(g, a, idbits, shmem, s);
+hipError_t launch_na(const GraphView& g, const SweepArgs& a, int idbits, size_t shmem,
+                     hipStream_t s) {
+  switch (a.n_out / NA) {
+    case 1: return launch_nr<NA, 1>(g, a, idbits, shmem, s);
+    case 2: return launch_nr<NA, 2>(g, a, idbits, shmem, s);
+    case 3: return launch_nr<NA, 3>(g, a, idbits, shmem, s);
+    case 4: return launch_nr<NA, 4>(g, a, idbits, shmem, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
@@ -451,14 +469,14 @@ hipError_t launch_prune_u8(const GraphView& g, const SweepArgs& a_in, DevCounter
   const int stride = u_stride(g.d);
   const size_t shmem = (size_t)max(65 * stride, kSTileBytes) + (64 + 68) * sizeof(int32_t);
   switch (a.n_alpha) {
-    case 1: return launch_cap<1>(g, a, idbits, shmem, s);
-    case 2: return launch_cap<2>(g, a, idbits, shmem, s);
-    case 3: return launch_cap<3>(g, a, idbits, shmem, s);
-    case 4: return launch_cap<4>(g, a, idbits, shmem, s);
-    case 5: return launch_cap<5>(g, a, idbits, shmem, s);
-    case 6: return launch_cap<6>(g, a, idbits, shmem, s);
-    case 7: return launch_cap<7>(g, a, idbits, shmem, s);
-    case 8: return launch_cap<8>(g, a, idbits, shmem, s);
+    case 1: return launch_na<1>(g, a, idbits, shmem, s);
+    case 2: return launch_na<2>(g, a, idbits, shmem, s);
+    case 3: return launch_na<3>(g, a, idbits, shmem, s);
+    case 4: return launch_na<4>(g, a, idbits, shmem, s);
+    case 5: return launch_na<5>(g, a, idbits, shmem, s);
+    case 6: return launch_na<6>(g, a, idbits, shmem, s);
+    case 7: return launch_na<7>(g, a, idbits, shmem, s);
+    case 8: return launch_na<8>(g, a, idbits, shmem, s);
     default: return hipErrorInvalidValue;
   }
 }
