@@ -300,34 +300,38 @@ __device__ __forceinline__ void node_back(const Tile& tl, const SweepArgs& a, in
     cnt[ai] = 0;
   }
   const int lbase = (lane & 31) + 1024 * (lane >> 5);
-  while (true) {
-    uint32_t row[NA];
-    uint64_t any = 0;
+  // Chain k steps: keep its lowest survivor i, read row i of the count tile,
+  // drop i itself (its count passes every threshold) and what it prunes.
+  // Phase s advances chains s..NA-1 in lockstep while chain s has survivors;
+  // chains are in ascending alpha and usually finish in that order, so the
+  // phases skip most steps of finished chains (a chain that finishes early
+  // only repeats harmless steps on an empty mask).
 #pragma unroll
-    for (int ai = 0; ai < NA; ++ai) {
-      // i = lowest surviving rank (s_ff1 gives -1 for an empty mask; clamping
-      // to rank 0 then only re-sets a bit that is already kept, or that the
-      // final mask with the valid ranks removes).
-      const uint64_t al = uniform_u64(alive[ai]);
-      int i;
-      asm("s_ff1_i32_b64 %0, %1" : "=s"(i) : "s"(al));
-      i = max(i, 0);
-      uint64_t k = uniform_u64(kept[ai]);
-      asm("s_bitset1_b64 %0, %1" : "+s"(k) : "s"(i));
-      kept[ai] = k;
-      if (CAP) {
-        cnt[ai] += alive[ai] != 0 ? 1 : 0;
-        if (cnt[ai] >= rmax[ai]) alive[ai] = 0;        // stop right after the R-th keep
+  for (int s0 = 0; s0 < NA; ++s0) {
+    while (alive[s0] != 0) {
+      uint32_t row[NA];
+#pragma unroll
+      for (int ai = s0; ai < NA; ++ai) {
+        // s_ff1 gives -1 for an empty mask; clamping to rank 0 then only
+        // re-sets a bit that is already kept, or that the final mask with
+        // the valid ranks removes.
+        const uint64_t al = uniform_u64(alive[ai]);
+        int i;
+        asm("s_ff1_i32_b64 %0, %1" : "=s"(i) : "s"(al));
+        i = max(i, 0);
+        uint64_t k = uniform_u64(kept[ai]);
+        asm("s_bitset1_b64 %0, %1" : "+s"(k) : "s"(i));
+        kept[ai] = k;
+        if (CAP) {
+          cnt[ai] += al != 0 ? 1 : 0;
+          if (cnt[ai] >= rmax[ai]) alive[ai] = 0;        // stop right after the R-th keep
+        }
+        row[ai] = tl.C[i * 32 + lbase];
       }
-      row[ai] = tl.C[i * 32 + lbase];
-    }
 #pragma unroll
-    for (int ai = 0; ai < NA; ++ai) {
-      // p* itself (S = 0 passes every threshold) and what it prunes
-      alive[ai] &= ~(uint64_t)__ballot(row[ai] > (uint32_t)ai);
-      any |= alive[ai];
+      for (int ai = s0; ai < NA; ++ai)
+        alive[ai] &= ~(uint64_t)__ballot(row[ai] > (uint32_t)ai);
     }
-    if (!any) break;
   }
 #pragma unroll
   for (int ai = 0; ai < NA; ++ai) kept[ai] &= f.valid_mask;
@@ -456,14 +460,17 @@ hipError_t launch_prune_u8(const GraphView& g, const SweepArgs& a_in, DevCounter
     }
     order[j + 1] = v;
   }
-  int rank_of[kMaxAlphas];
+  // outputs are alpha-major (o = alpha * n_R + iR); permute them with the alphas
+  const int nr = a_in.n_out / a_in.n_alpha;
   for (int k = 0; k < a_in.n_alpha; ++k) {
     a.num2[k] = a_in.num2[order[k]];
     a.den2[k] = a_in.den2[order[k]];
     a.ratio[k] = a_in.ratio[order[k]];
-    rank_of[order[k]] = k;
+    for (int ir = 0; ir < nr; ++ir) {
+      a.out[k * nr + ir] = a_in.out[order[k] * nr + ir];
+      a.out[k * nr + ir].alpha_idx = k;
+    }
   }
-  for (int o = 0; o < a_in.n_out; ++o) a.out[o].alpha_idx = rank_of[a_in.out[o].alpha_idx];
   int idbits = 1;
   while ((1ll << idbits) < g.n) ++idbits;
   const int stride = u_stride(g.d);
