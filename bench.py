@@ -31,6 +31,111 @@ METRIC = ("RP-Tuning prune nodes/s (+% HBM/MFMA roofline) vs plain FP32; "
 HBM_PEAK_GBS = 8000.0
 
 
+COPY_BYTES = 256 << 20
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SRC = {"u8": os.path.join(ROOT, "paper_2602_08097_amd", "csrc", "k_prune_u8.hip")}
+
+
+def source_digest(path):
+    import hashlib
+
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(dtype, n):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, if it was taken on the current kernel source and workload size."""
+    import numpy as np
+
+    path = os.path.join(PROFILES, "prune_u8_sift_u8_traffic.json")
+    if dtype != np.uint8 or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_sha256_16") != source_digest(KERNEL_SRC["u8"]) or t.get("n") != n:
+        return None
+    return t.get("traffic_bytes_per_launch")
+
+
+def _read_csvs(root, suffix):
+    import csv
+    import glob
+
+    rows = []
+    for path in sorted(glob.glob(os.path.join(root, "**", f"*{suffix}"), recursive=True)):
+        with open(path) as f:
+            rows.extend(csv.DictReader(f))
+    return rows
+
+
+def _col(row, *names):
+    low = {k.lower(): k for k in row}
+    for nm in names:
+        if nm.lower() in low:
+            return row[low[nm.lower()]]
+    raise KeyError(f"none of {names} in {list(row)}")
+
+
+def summarize_profile(root):
+    """Summarise the three rocprofv3 runs under root (trace/, fetch/, write/)."""
+    out = os.path.join(root, "summary")
+    os.makedirs(out, exist_ok=True)
+    stats = _read_csvs(os.path.join(root, "trace"), "kernel_stats.csv")
+    lines = ["| kernel | calls | average (us) | total (ms) |", "|---|---|---|---|"]
+    prune_avg_ns = None
+    for r in stats:
+        name = _col(r, "Name", "KERNEL_NAME")
+        calls = int(_col(r, "Calls"))
+        avg = float(_col(r, "AverageNs", "Average_Ns", "AVERAGE_NS"))
+        tot = float(_col(r, "TotalDurationNs", "Total_Duration_Ns", "TOTAL_DURATION_NS"))
+        if "prune" in name or calls >= 3:
+            lines.append(f"| {name[:90]} | {calls} | {avg / 1e3:.1f} | {tot / 1e6:.2f} |")
+        if "prune_u8_kernel" in name:
+            prune_avg_ns = avg
+    res = {"prune_u8_avg_ns": prune_avg_ns}
+    for tag, counter in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
+        rows = _read_csvs(os.path.join(root, tag), "counter_collection.csv")
+        per = {}
+        for r in rows:
+            if _col(r, "Counter_Name", "COUNTER_NAME") != counter:
+                continue
+            name = _col(r, "Kernel_Name", "KERNEL_NAME")
+            disp = _col(r, "Dispatch_Id", "DISPATCH_ID")
+            per.setdefault(name, {}).setdefault(disp, 0.0)
+            per[name][disp] += float(_col(r, "Counter_Value", "COUNTER_VALUE"))
+        for name, d in per.items():
+            vals = list(d.values())
+            key = "prune" if "prune_u8_kernel" in name else (
+                "copy" if ("copy" in name.lower() or "elementwise" in name.lower()) else None)
+            if key:
+                res[f"{tag}_{key}_kib"] = sum(vals) / len(vals)
+                res[f"{tag}_{key}_name"] = name[:120]
+    with open(os.path.join(out, "kernel_stats.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    with open(os.path.join(out, "counters.json"), "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res, indent=1))
+
+
+def load_or_build(args, spec, dev):
+    import numpy as np
+
+    import workloads
+
+    if args.cache and os.path.exists(args.cache):
+        z = np.load(args.cache, allow_pickle=False)
+        tg = z["targets"] if z["targets"].size else None
+        return workloads.Workload(spec, z["X"], z["Q"], z["knn"], z["knn_deg"], int(z["start"]),
+                                  tg, z["sample"])
+    w = workloads.build(args.config, n=args.n, nq=args.nq, device=dev)
+    if args.cache:
+        np.savez(args.cache, X=w.X, Q=w.Q, knn=w.knn, knn_deg=w.knn_deg, start=np.int64(w.start),
+                 targets=w.targets if w.targets is not None else np.zeros(0, np.int32),
+                 sample=w.sample)
+    return w
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -78,8 +183,9 @@ def cpu_baseline(w, spec, budget_s):
     import numpy as np
 
     import oracle
+    import workloads
 
-    nodes = w.sample
+    nodes = workloads.node_sample(w.X.shape[0], 40_000)
     # the oracle builds its own base rows for the sample from the K-NN lists
     b_nbr, b_deg, _ = oracle.prune_graph(w.X, w.knn, w.knn_deg, *spec.base_alpha, spec.base_R,
                                          nodes=nodes)
@@ -116,7 +222,22 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-search", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="profiling run: a 256 MiB device copy for counter calibration, then "
+                         "the timed sweep only (no plain/search/CPU legs)")
+    ap.add_argument("--cache", metavar="NPZ",
+                    help="load the generated workload from NPZ if present, else generate and save "
+                         "it there (for repeated profiler runs)")
+    ap.add_argument("--summarize-profile", metavar="DIR",
+                    help="summarise rocprofv3 output under DIR (trace, fetch, write runs) into "
+                         "DIR/summary and exit")
     args = ap.parse_args()
+
+    if args.summarize_profile:
+        summarize_profile(args.summarize_profile)
+        return
+    if args.profile:
+        args.no_plain = args.no_search = args.no_cpu = True
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -131,9 +252,16 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.profile:
+        # counter calibration: a plain device copy of a known size
+        src = torch.randint(0, 255, (COPY_BYTES,), dtype=torch.uint8, device=dev)
+        for _ in range(3):
+            dst = src.clone()
+        torch.cuda.synchronize()
+        del src, dst
     spec = workloads.CONFIGS[args.config]
     t0 = time.time()
-    w = workloads.build(args.config, n=args.n, nq=args.nq, device=dev)
+    w = load_or_build(args, spec, dev)
     n, d = w.X.shape
     log(f"workload {spec.name}: n={n} d={d} ({time.time() - t0:.1f} s incl. exact {spec.knn_k}-NN)")
 
@@ -178,7 +306,8 @@ def main():
     abytes = algorithmic_bytes(deg_np, d, esz, Rs_out)
     achieved = abytes / (avg_kernel_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(w.X.dtype, n),
                 "kernel": "prune_u8_kernel" if w.X.dtype == np.uint8 else "prune_plain_kernel",
                 "algorithmic_bytes_per_launch": abytes,
                 "kernel_ms_avg": round(avg_kernel_ms, 4)}
