@@ -106,11 +106,7 @@ def summarize_profile(root):
             per[name][disp] += float(_col(r, "Counter_Value", "COUNTER_VALUE"))
         for name, d in per.items():
             vals = list(d.values())
-            key = "prune" if "prune_u8_kernel" in name else (
-                "copy" if ("copy" in name.lower() or "elementwise" in name.lower()) else None)
-            if key:
-                res[f"{tag}_{key}_kib"] = sum(vals) / len(vals)
-                res[f"{tag}_{key}_name"] = name[:120]
+            res[f"{tag} KiB/dispatch (n={len(vals)}): {name[:100]}"] = sum(vals) / len(vals)
     with open(os.path.join(out, "kernel_stats.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
     with open(os.path.join(out, "counters.json"), "w") as f:
