@@ -250,11 +250,12 @@ def main():
     torch.cuda.set_device(dev)
     if args.profile:
         # counter calibration: a plain device copy of a known size
+        # (a fill kernel writes COPY_BYTES; a reduction reads COPY_BYTES)
         src = torch.randint(0, 255, (COPY_BYTES,), dtype=torch.uint8, device=dev)
         for _ in range(3):
-            dst = src.clone()
+            total = src.sum(dtype=torch.int64)
         torch.cuda.synchronize()
-        del src, dst
+        del src, total
     spec = workloads.CONFIGS[args.config]
     t0 = time.time()
     w = load_or_build(args, spec, dev)
