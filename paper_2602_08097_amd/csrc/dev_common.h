@@ -78,4 +78,105 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
   return v;
 }
 
+// Lane exchange with partner lane ^ J (J a power of two).
+template <int J>
+__device__ __forceinline__ int xchg(int v) {
+  if constexpr (J == 1) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+  else if constexpr (J == 2) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+  else if constexpr (J == 4) return __builtin_amdgcn_ds_swizzle(v, 0x101F);
+  else if constexpr (J == 8) return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);
+  else if constexpr (J == 16) return __builtin_amdgcn_ds_swizzle(v, 0x401F);
+  else return __shfl_xor(v, 32, 64);
+}
+
+template <int K, int J>
+__device__ __forceinline__ uint64_t bitonic_step(uint64_t key, int lane) {
+  const int lo = xchg<J>((int)(uint32_t)key);
+  const int hi = xchg<J>((int)(uint32_t)(key >> 32));
+  const uint64_t other = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+  const bool take_min = ((lane & J) == 0) == ((lane & K) == 0);
+  const uint64_t mn = key < other ? key : other;
+  const uint64_t mx = key < other ? other : key;
+  return take_min ? mn : mx;
+}
+
+// Ascending bitonic sort of one 64-bit key per lane across the wavefront.
+__device__ __forceinline__ uint64_t wave_sort(uint64_t k, int lane) {
+  k = bitonic_step<2, 1>(k, lane);
+  k = bitonic_step<4, 2>(k, lane);
+  k = bitonic_step<4, 1>(k, lane);
+  k = bitonic_step<8, 4>(k, lane);
+  k = bitonic_step<8, 2>(k, lane);
+  k = bitonic_step<8, 1>(k, lane);
+  k = bitonic_step<16, 8>(k, lane);
+  k = bitonic_step<16, 4>(k, lane);
+  k = bitonic_step<16, 2>(k, lane);
+  k = bitonic_step<16, 1>(k, lane);
+  k = bitonic_step<32, 16>(k, lane);
+  k = bitonic_step<32, 8>(k, lane);
+  k = bitonic_step<32, 4>(k, lane);
+  k = bitonic_step<32, 2>(k, lane);
+  k = bitonic_step<32, 1>(k, lane);
+  k = bitonic_step<64, 32>(k, lane);
+  k = bitonic_step<64, 16>(k, lane);
+  k = bitonic_step<64, 8>(k, lane);
+  k = bitonic_step<64, 4>(k, lane);
+  k = bitonic_step<64, 2>(k, lane);
+  k = bitonic_step<64, 1>(k, lane);
+  return k;
+}
+
+// Ascending bitonic sort of (hi, lo) pairs across the wavefront, compared
+// lexicographically.
+template <int K, int J>
+__device__ __forceinline__ void bitonic_step2(uint64_t& hi, uint32_t& lo, int lane) {
+  const int oh0 = xchg<J>((int)(uint32_t)hi);
+  const int oh1 = xchg<J>((int)(uint32_t)(hi >> 32));
+  const uint32_t olo = (uint32_t)xchg<J>((int)lo);
+  const uint64_t ohi = ((uint64_t)(uint32_t)oh1 << 32) | (uint32_t)oh0;
+  const bool mine_less = hi < ohi || (hi == ohi && lo < olo);
+  const bool take_min = ((lane & J) == 0) == ((lane & K) == 0);
+  if (take_min != mine_less) {
+    hi = ohi;
+    lo = olo;
+  }
+}
+
+__device__ __forceinline__ void wave_sort2(uint64_t& hi, uint32_t& lo, int lane) {
+  bitonic_step2<2, 1>(hi, lo, lane);
+  bitonic_step2<4, 2>(hi, lo, lane);
+  bitonic_step2<4, 1>(hi, lo, lane);
+  bitonic_step2<8, 4>(hi, lo, lane);
+  bitonic_step2<8, 2>(hi, lo, lane);
+  bitonic_step2<8, 1>(hi, lo, lane);
+  bitonic_step2<16, 8>(hi, lo, lane);
+  bitonic_step2<16, 4>(hi, lo, lane);
+  bitonic_step2<16, 2>(hi, lo, lane);
+  bitonic_step2<16, 1>(hi, lo, lane);
+  bitonic_step2<32, 16>(hi, lo, lane);
+  bitonic_step2<32, 8>(hi, lo, lane);
+  bitonic_step2<32, 4>(hi, lo, lane);
+  bitonic_step2<32, 2>(hi, lo, lane);
+  bitonic_step2<32, 1>(hi, lo, lane);
+  bitonic_step2<64, 32>(hi, lo, lane);
+  bitonic_step2<64, 16>(hi, lo, lane);
+  bitonic_step2<64, 8>(hi, lo, lane);
+  bitonic_step2<64, 4>(hi, lo, lane);
+  bitonic_step2<64, 2>(hi, lo, lane);
+  bitonic_step2<64, 1>(hi, lo, lane);
+}
+
+// A wave-uniform 64-bit value pinned to scalar registers.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
+  int lo = __shfl((int)(uint32_t)v, src, 64);
+  int hi = __shfl((int)(uint32_t)(v >> 32), src, 64);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
 }  // namespace rp

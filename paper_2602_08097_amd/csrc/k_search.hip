@@ -1,31 +1,61 @@
 // k_search.hip -- GreedySearch(s, q, k, L) (Algorithm 2), one wavefront per query.
 //
-// The search list is kept in LDS sorted by (S(q, .), id) with a visited flag
-// per entry, in two ping-pong buffers.  One expansion:
+// The search list lives in LDS, sorted by the key (S(q, v), v) with a visited
+// flag per entry, in two ping-pong buffers.  One expansion:
 //   1. p* = the first unvisited entry of the sorted list (= argmin over L \ V);
-//   2. the lanes read N_out(p*) (64 ids per pass), compute S(q, j) exactly
-//      (integers for uint8, canonical FP64 for float32), drop repeated ids and
-//      ids already in the list (binary search on (S, id): S is a function of
-//      the id), and, once the list is full, ids that fall behind its L-th
-//      entry (the truncation would drop them at once);
-//   3. the survivors are ranked and merged into the list, which is cut to L.
+//   2. the lanes read N_out(p*) (64 ids per pass) and compute S(q, j) exactly:
+//      uint8 points as |q|^2 + |x_j|^2 - 2 <q, x_j> with 4-way byte dot
+//      products on 16-byte row loads (|x_j|^2 precomputed per point);
+//      float32 points as the canonical FP64 value;
+//   3. the 64 keys are sorted across the wavefront (DPP bitonic network), so
+//      repeated ids become adjacent; ids already in the list are found by a
+//      lower-bound search of their key (S is a function of the id), and once
+//      the list is full, ids behind its L-th entry are dropped (the truncation
+//      would drop them at once);
+//   4. the survivors, still in key order after compaction, are merged into
+//      the list, which is cut at L.
 // Algorithm 2 also remembers visited vertices that the truncation evicted.
 // Such a vertex can never re-enter the list: once the list holds L entries
 // its L-th entry only moves closer, and the evicted vertex was behind it.
 // The per-entry flags therefore carry the whole visited set that matters.
+//
+// Keys are (hi, lo) pairs compared lexicographically: hi = S (uint8 points) or
+// the bit pattern of the non-negative FP64 S (float32 points, which orders as
+// an unsigned integer); lo = the vertex id.
 #include "dev_common.h"
 
 namespace rp {
 
-template <int DT>
-__device__ __forceinline__ double query_sq(const GraphView& g, const void* q, int64_t j) {
-  if (DT == RP_U8) {
-    const uint8_t* X = (const uint8_t*)g.X;
-    return (double)sq_u8((const uint8_t*)q, X + j * g.d, g.d);
-  } else {
-    const float* X = (const float*)g.X;
-    return canon_sq_f32((const float*)q, X + j * g.d, g.d);
+namespace {
+
+// Byte offset of the query row in the search kernel's LDS (16-byte aligned).
+__host__ __device__ inline size_t search_query_offset(int cap) {
+  const size_t off = (size_t)cap * 2 * 8 + kWave * 8 + (size_t)cap * 2 * 4 + kWave * 4 +
+                     kWave * 4 + (size_t)cap * 2;
+  return (off + 15) & ~(size_t)15;
+}
+
+__device__ __forceinline__ bool key_less(uint64_t ah, uint32_t al, uint64_t bh, uint32_t bl) {
+  return ah < bh || (ah == bh && al < bl);
+}
+
+// S(q, x_j) for uint8 points: q in LDS (broadcast reads), 16-byte row loads.
+__device__ __forceinline__ uint32_t sq_u8_q(const uint8_t* __restrict__ qs,
+                                            const uint8_t* __restrict__ x, int d, uint32_t qq,
+                                            uint32_t xx) {
+  uint32_t dot = 0;
+  int k = 0;
+  if (((d & 15) | ((uintptr_t)x & 15)) == 0)  // 16-byte aligned rows
+  for (; k + 16 <= d; k += 16) {
+    const uint4 a = *(const uint4*)(qs + k);
+    const uint4 b = *(const uint4*)(x + k);
+    dot = __builtin_amdgcn_udot4(a.x, b.x, dot, false);
+    dot = __builtin_amdgcn_udot4(a.y, b.y, dot, false);
+    dot = __builtin_amdgcn_udot4(a.z, b.z, dot, false);
+    dot = __builtin_amdgcn_udot4(a.w, b.w, dot, false);
   }
+  for (; k < d; ++k) dot += (uint32_t)qs[k] * x[k];
+  return qq + xx - 2u * dot;
 }
 
 template <int DT>
@@ -34,36 +64,50 @@ __global__ __launch_bounds__(64) void search_kernel(GraphView g, const void* __r
                                                     int32_t* __restrict__ out_ids,
                                                     double* __restrict__ out_dist,
                                                     int32_t* __restrict__ out_hops) {
-  extern __shared__ double smem[];
+  extern __shared__ __align__(16) uint64_t smem[];
   const int cap = L + kWave;
-  double* bS0 = smem;
-  double* bS1 = bS0 + cap;
-  double* cS = bS1 + cap;        // 64 new candidates (compacted)
-  double* sS = cS + kWave;       // 64 new candidates (sorted)
-  int32_t* bI0 = (int32_t*)(sS + kWave);
-  int32_t* bI1 = bI0 + cap;
-  int32_t* cI = bI1 + cap;
-  int32_t* cLb = cI + kWave;
-  int32_t* sI = cLb + kWave;
-  int32_t* sLb = sI + kWave;
-  uint8_t* bV0 = (uint8_t*)(sLb + kWave);
+  uint8_t* base = (uint8_t*)smem;
+  uint64_t* bH0 = (uint64_t*)base;
+  uint64_t* bH1 = bH0 + cap;
+  uint64_t* nH = bH1 + cap;                 // new candidates, compacted (sorted)
+  uint32_t* bL0 = (uint32_t*)(nH + kWave);
+  uint32_t* bL1 = bL0 + cap;
+  uint32_t* nL = bL1 + cap;
+  int32_t* nLb = (int32_t*)(nL + kWave);    // insertion position in the old list
+  uint8_t* bV0 = (uint8_t*)(nLb + kWave);
   uint8_t* bV1 = bV0 + cap;
+  uint8_t* qs = base + search_query_offset(cap);  // query row, 16-byte aligned
 
   const int lane = threadIdx.x;
   const int64_t qi = blockIdx.x;
+  const int d = g.d;
   const size_t esz = DT == RP_U8 ? 1 : 4;
-  const void* q = (const char*)Q + (size_t)qi * g.d * esz;
+  const uint8_t* qg = (const uint8_t*)Q + (size_t)qi * d * esz;
+  for (int t = lane; t < (int)(d * esz); t += kWave) qs[t] = qg[t];
+  __syncthreads();
+  uint32_t qq = 0;
+  if (DT == RP_U8) {
+    for (int t = 0; t < d; ++t) qq += (uint32_t)qs[t] * qs[t];
+  }
 
-  double* bS = bS0;
-  int32_t* bI = bI0;
+  auto dist = [&](int64_t j) -> uint64_t {
+    if (DT == RP_U8) {
+      return (uint64_t)sq_u8_q(qs, (const uint8_t*)g.X + j * d, d, qq, g.norms[j]);
+    } else {
+      const double s = canon_sq_f32((const float*)qs, (const float*)g.X + j * d, d);
+      return (uint64_t)__double_as_longlong(s);
+    }
+  };
+
+  uint64_t* bH = bH0;
+  uint32_t* bL = bL0;
   uint8_t* bV = bV0;
-  double* nS = bS1;
-  int32_t* nI = bI1;
-  uint8_t* nV = bV1;
-
+  uint64_t* oH = bH1;
+  uint32_t* oL = bL1;
+  uint8_t* oV = bV1;
   if (lane == 0) {
-    bS[0] = query_sq<DT>(g, q, g.start);
-    bI[0] = g.start;
+    bH[0] = dist(g.start);
+    bL[0] = (uint32_t)g.start;
     bV[0] = 0;
   }
   int cnt = 1;
@@ -76,15 +120,15 @@ __global__ __launch_bounds__(64) void search_kernel(GraphView g, const void* __r
     // 1. first unvisited entry
     int pos = -1;
     for (int c = 0; c < cnt; c += kWave) {
-      int t = c + lane;
-      unsigned long long mask = __ballot(t < cnt && !bV[t]);
+      const int t = c + lane;
+      const uint64_t mask = __ballot(t < cnt && !bV[t]);
       if (mask) {
         pos = c + __ffsll((long long)mask) - 1;
         break;
       }
     }
     if (pos < 0) break;
-    const int pstar = bI[pos];
+    const int pstar = (int)bL[pos];
     __syncthreads();
     if (lane == 0) bV[pos] = 1;
     ++hops;
@@ -93,97 +137,94 @@ __global__ __launch_bounds__(64) void search_kernel(GraphView g, const void* __r
 
     for (int c0 = 0; c0 < m; c0 += kWave) {
       const int t = c0 + lane;
-      int j = t < m ? row[t] : -1;
-      // repeated ids within this pass: keep the first occurrence
-      bool keep = j >= 0;
-      for (int u = 0; u < kWave; ++u) {
-        int other = __shfl(j, u, 64);
-        if (u < lane && other == j) keep = false;
+      const int j = t < m ? row[t] : -1;
+      // 2. distances
+      uint64_t kh = ~0ull;
+      uint32_t kl = ~0u;
+      if (j >= 0) {
+        kh = dist(j);
+        kl = (uint32_t)j;
       }
-      double s = 0.0;
+      // 3. sort the keys; repeats become adjacent
+      wave_sort2(kh, kl, lane);
+      const uint64_t ph = shfl_u64(kh, lane > 0 ? lane - 1 : 0);
+      const uint32_t pl = (uint32_t)__shfl((int)kl, lane > 0 ? lane - 1 : 0, 64);
+      bool keep = kl != ~0u && !(lane > 0 && ph == kh && pl == kl);
       int lb = 0;
       if (keep) {
-        s = query_sq<DT>(g, q, j);
-        // lower bound: number of list entries strictly before (s, j)
-        int lo = 0, hi = cnt;
+        int lo = 0, hi = cnt;  // entries strictly before (kh, kl)
         while (lo < hi) {
-          int mid = (lo + hi) >> 1;
-          if (before_f64(bS[mid], bI[mid], s, j)) lo = mid + 1;
+          const int mid = (lo + hi) >> 1;
+          if (key_less(bH[mid], bL[mid], kh, kl)) lo = mid + 1;
           else hi = mid;
         }
         lb = lo;
-        if (lb < cnt && bI[lb] == j) keep = false;            // already in the list
+        if (lb < cnt && bL[lb] == kl) keep = false;          // already in the list
         if (keep && cnt == L && lb >= L) keep = false;        // behind the L-th entry
       }
-      unsigned long long km = __ballot(keep);
+      const uint64_t km = __ballot(keep);
       const int nc = __popcll(km);
+      if (nc == 0) continue;  // uniform
       if (keep) {
-        int slot = __popcll(km & ((1ull << lane) - 1ull));
-        cS[slot] = s;
-        cI[slot] = j;
-        cLb[slot] = lb;
+        const int slot = __popcll(km & ((1ull << lane) - 1ull));
+        nH[slot] = kh;
+        nL[slot] = kl;
+        nLb[slot] = lb;
       }
       __syncthreads();
-      if (nc == 0) continue;
-      // rank the new candidates by (S, id)
-      if (lane < nc) {
-        double ms = cS[lane];
-        int mi = cI[lane];
-        int r = 0;
-        for (int u = 0; u < nc; ++u) r += before_f64(cS[u], cI[u], ms, mi) ? 1 : 0;
-        sS[r] = ms;
-        sI[r] = mi;
-        sLb[r] = cLb[lane];
-      }
-      __syncthreads();
-      // merge into the other buffer, cut at L
+      // 4. merge into the other buffer, cut at L
       for (int i = lane; i < cnt; i += kWave) {
-        double es = bS[i];
-        int ei = bI[i];
-        int lo = 0, hi = nc;  // new candidates strictly before entry i
+        int lo = 0, hi = nc;  // new candidates whose insertion position is <= i
         while (lo < hi) {
-          int mid = (lo + hi) >> 1;
-          if (before_f64(sS[mid], sI[mid], es, ei)) lo = mid + 1;
+          const int mid = (lo + hi) >> 1;
+          if (nLb[mid] <= i) lo = mid + 1;
           else hi = mid;
         }
-        int dst = i + lo;
+        const int dst = i + lo;
         if (dst < L) {
-          nS[dst] = es;
-          nI[dst] = ei;
-          nV[dst] = bV[i];
+          oH[dst] = bH[i];
+          oL[dst] = bL[i];
+          oV[dst] = bV[i];
         }
       }
       if (lane < nc) {
-        int dst = lane + sLb[lane];
+        const int dst = lane + nLb[lane];
         if (dst < L) {
-          nS[dst] = sS[lane];
-          nI[dst] = sI[lane];
-          nV[dst] = 0;
+          oH[dst] = nH[lane];
+          oL[dst] = nL[lane];
+          oV[dst] = 0;
         }
       }
       cnt = min(L, cnt + nc);
       __syncthreads();
-      double* ts = bS; bS = nS; nS = ts;
-      int32_t* ti = bI; bI = nI; nI = ti;
-      uint8_t* tv = bV; bV = nV; nV = tv;
+      uint64_t* th = bH; bH = oH; oH = th;
+      uint32_t* tl = bL; bL = oL; oL = tl;
+      uint8_t* tv = bV; bV = oV; oV = tv;
     }
     __syncthreads();
   }
 
   for (int t = lane; t < k; t += kWave) {
-    out_ids[qi * k + t] = t < cnt ? bI[t] : -1;
-    if (out_dist) out_dist[qi * k + t] = t < cnt ? bS[t] : -1.0;
+    out_ids[qi * k + t] = t < cnt ? (int32_t)bL[t] : -1;
+    if (out_dist) {
+      double dv = -1.0;
+      if (t < cnt) dv = DT == RP_U8 ? (double)bH[t] : __longlong_as_double((long long)bH[t]);
+      out_dist[qi * k + t] = dv;
+    }
   }
   if (lane == 0 && out_hops) out_hops[qi] = hops;
 }
+
+}  // namespace
 
 hipError_t launch_search(const GraphView& g, const void* Q, int64_t nq, int32_t k, int32_t L,
                          int32_t* out_ids, double* out_dist, int32_t* out_hops,
                          hipStream_t s) {
   if (nq == 0) return hipSuccess;
   const size_t cap = (size_t)L + kWave;
-  const size_t shmem = cap * 2 * sizeof(double) + 2 * kWave * sizeof(double) +
-                       cap * 2 * sizeof(int32_t) + 4 * kWave * sizeof(int32_t) + cap * 2;
+  const size_t esz = g.dtype == RP_U8 ? 1 : 4;
+  // keys (hi, lo), insertion positions, visited flags, then the query row
+  const size_t shmem = search_query_offset((int)cap) + (size_t)g.d * esz;
   dim3 grid((unsigned)nq), block(kWave);
   if (g.dtype == RP_U8)
     hipLaunchKernelGGL(search_kernel<RP_U8>, grid, block, shmem, s, g, Q, k, L, out_ids,

@@ -24,6 +24,25 @@ __global__ void validate_kernel(GraphView g, DevCounters* ctr) {
   if ((threadIdx.x & (kWave - 1)) == 0 && cnt) atomicAdd(&ctr->errors, cnt);
 }
 
+// |x_p|^2 of every uint8 point (exact), for the search distances.
+__global__ void norms_u8_kernel(const uint8_t* __restrict__ X, int64_t n, int d,
+                                uint32_t* __restrict__ norms) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const uint8_t* x = X + p * d;
+  uint32_t acc = 0;
+  for (int k = 0; k < d; ++k) acc += (uint32_t)x[k] * x[k];
+  norms[p] = acc;
+}
+
+hipError_t launch_norms_u8(const GraphView& g, uint32_t* norms, hipStream_t s) {
+  const int block = 256;
+  const int64_t grid = (g.n + block - 1) / block;
+  hipLaunchKernelGGL(norms_u8_kernel, dim3((unsigned)grid), dim3(block), 0, s,
+                     (const uint8_t*)g.X, g.n, g.d, norms);
+  return hipGetLastError();
+}
+
 hipError_t launch_validate(const GraphView& g, DevCounters* ctr, hipStream_t s) {
   const int block = 256;
   const int64_t grid = (g.n + block - 1) / block;
