@@ -146,6 +146,16 @@ def algorithmic_bytes(deg, d, esz, Rs_per_output):
     return int((4 * (m + 1) + (m + 1) * d * esz).sum() + per_out * m.shape[0])
 
 
+def batched_kernel_name(dtype, r_max, d):
+    """The kernel the sweep dispatches to for this graph shape."""
+    import numpy as np
+
+    if dtype == np.uint8:
+        return "prune_u8_kernel" if r_max <= 64 and d % 16 == 0 and d <= 256 else \
+            "prune_plain_kernel"
+    return "prune_f32_kernel" if r_max <= 64 else "prune_plain_kernel"
+
+
 def exact_gt_u8(X, Q, k, chunk=1024):
     """Exact top-k by (S, id) for uint8 data on the GPU (integer keys)."""
     import torch
@@ -163,6 +173,37 @@ def exact_gt_u8(X, Q, k, chunk=1024):
         vals, _ = torch.topk(key, k, dim=1, largest=False, sorted=True)
         out.append((vals & ((1 << idbits) - 1)).to(torch.int32))
     return torch.cat(out)
+
+
+def exact_gt_f32(X, Q, k, chunk=256):
+    """Top-k by FP32 squared distance (used for recall only)."""
+    import torch
+
+    nx = (X * X).sum(1)
+    out = []
+    for a in range(0, Q.shape[0], chunk):
+        q = Q[a:a + chunk]
+        dist = nx[None, :] - 2.0 * (q @ X.T) + (q * q).sum(1)[:, None]
+        out.append(torch.topk(dist, k, dim=1, largest=False, sorted=True).indices.to(torch.int32))
+    return torch.cat(out)
+
+
+def reachable_fraction(nbr, deg, start):
+    """Fraction of vertices reachable from the start vertex (BFS on the GPU)."""
+    import torch
+
+    n, r = nbr.shape
+    seen = torch.zeros(n, dtype=torch.bool, device=nbr.device)
+    seen[start] = True
+    frontier = torch.tensor([start], dtype=torch.int64, device=nbr.device)
+    cols = torch.arange(r, device=nbr.device)
+    while frontier.numel():
+        rows = nbr[frontier]
+        nxt = rows[cols[None, :] < deg[frontier][:, None]].long()
+        nxt = torch.unique(nxt[~seen[nxt]])
+        seen[nxt] = True
+        frontier = nxt
+    return float(seen.float().mean().item())
 
 
 def recall(ids, gt, k):
@@ -267,6 +308,12 @@ def main():
     kdeg = torch.from_numpy(w.knn_deg).to(dev)
     g_knn = Graph(X, knn, kdeg, w.start)
     base_nbr, base_deg = g_knn.prune(spec.base_alpha, spec.base_R)
+    if w.targets is not None:
+        # uneven out-degrees: keep the first min(t_p, deg) ids of each base list
+        base_deg = torch.minimum(base_deg, torch.from_numpy(w.targets).to(dev))
+        cols = torch.arange(spec.base_R, device=dev, dtype=torch.int32)
+        base_nbr = torch.where(cols[None, :] < base_deg[:, None], base_nbr,
+                               torch.full_like(base_nbr, -1))
     torch.cuda.synchronize()
     g = g_knn.derive(base_nbr, base_deg)
     deg_np = base_deg.cpu().numpy()
@@ -280,6 +327,7 @@ def main():
     for _ in range(args.warmup):
         g.prune_sweep(spec.sweep, spec.Rs, outs=outs)
     torch.cuda.synchronize()
+    g.counters(reset=True)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(args.steps)]
     t_start = time.perf_counter()
@@ -290,6 +338,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     kern_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
+    ctr = g.counters()
     ms_per_step = wall * 1e3 / args.steps
     value = n / (wall / args.steps)
     avg_kernel_ms = float(np.mean(kern_ms))
@@ -305,7 +354,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(w.X.dtype, n),
-                "kernel": "prune_u8_kernel" if w.X.dtype == np.uint8 else "prune_plain_kernel",
+                "kernel": batched_kernel_name(w.X.dtype, spec.base_R, d),
                 "algorithmic_bytes_per_launch": abytes,
                 "kernel_ms_avg": round(avg_kernel_ms, 4)}
 
@@ -337,13 +386,18 @@ def main():
     if not args.no_search and w.Q.shape[0] > 0:
         Q = torch.from_numpy(w.Q).to(dev)
         k = spec.k
-        gt = exact_gt_u8(X, Q, k) if w.X.dtype == np.uint8 else None
+        gt = exact_gt_u8(X, Q, k) if w.X.dtype == np.uint8 else exact_gt_f32(X, Q, k)
         res = []
         graphs = [("base", g, None)]
         for o in range(0, len(outs), nr):
             graphs.append((f"alpha={spec.sweep[o // nr][0]}/{spec.sweep[o // nr][1]}",
                            g.derive(outs[o][0], outs[o][1]), None))
+        reach = {}
         for name, gg, _ in graphs:
+            nb_, dg_ = (base_nbr, base_deg) if name == "base" else outs[
+                nr * [x[0] for x in graphs[1:]].index(name)]
+            reach[name] = reachable_fraction(nb_, dg_, w.start)
+            log(f"graph {name}: {100 * reach[name]:.2f}% of vertices reachable from the start")
             for L in spec.Ls:
                 gg.search(Q, k, L, want_dist=False)
                 torch.cuda.synchronize()
@@ -362,7 +416,7 @@ def main():
                             "batch_ms_p50": ms, "batch_ms_max": float(np.max(lat)),
                             "recall_at_k": rec, "mean_hops": float(hops.float().mean().item())})
                 log(f"search {name} L={L}: {Q.shape[0] / (ms * 1e-3):.3e} QPS, recall {rec}")
-        search = {"k": k, "nq": int(Q.shape[0]), "results": res}
+        search = {"k": k, "nq": int(Q.shape[0]), "reachable_fraction": reach, "results": res}
 
     cpu = None
     if not args.no_cpu:
@@ -388,6 +442,7 @@ def main():
                                f"{spec.base_alpha[1]} R={spec.base_R}; sweep alpha="
                                f"{[f'{a}/{b}' for a, b in spec.sweep]} R={list(spec.Rs)}",
                    "n": n, "d": d, "mean_base_degree": float(deg_np.mean()),
+                   "rechecks_per_node_alpha": ctr["rechecks"] / max(1, ctr["nodes"]),
                    "outputs_per_step": len(outs)},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -52,8 +52,10 @@ CONFIGS = {
     "sift_u8": Spec("sift_u8", 1_000_000, 128, "u8", 64, 128.0, 10.0, 20.0, False, 128,
                     (6, 5), 64, ((23, 20), (11, 10), (21, 20), (1, 1)), (64,), 10_000, 100,
                     (100, 150, 200, 300, 400), False, 20_000),
-    # 1M x 96 float32, 128 components, centres ~ N(0, I), sigma 1, unit-normalised.
-    "deep_f32": Spec("deep_f32", 1_000_000, 96, "f32", 128, 0.0, 1.0, 1.0, True, 128,
+    # 1M x 96 float32, 128 components, centres ~ N(0, 0.5^2 I), sigma 1, unit-normalised
+    # (with centres ~ N(0, I) the components separate after normalisation and the
+    # K-NN graph falls apart into one piece per component).
+    "deep_f32": Spec("deep_f32", 1_000_000, 96, "f32", 128, 0.0, 0.5, 1.0, True, 128,
                      (13, 10), 64,
                      ((1, 1), (26, 25), (109, 100), (113, 100), (117, 100), (121, 100),
                       (63, 50), (13, 10)), (64,), 10_000, 100, (100, 150, 200, 300, 400),
