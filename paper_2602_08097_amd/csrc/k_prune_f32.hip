@@ -1,29 +1,39 @@
-// k_prune_f32.hip -- batched RP-Tuning for float32 points: FP16 MFMA Gram tile
-// with a rigorous rounding bound and a canonical FP64 recheck.
+// k_prune_f32.hip -- batched RP-Tuning for float32 points: split-FP16 MFMA
+// Gram tile with a rigorous rounding band and a canonical FP64 recheck.
 //
 // One wavefront runs RobustPrune(p, N_out(p), alpha, R) (Algorithm 1) for one
-// vertex p at every alpha of a sweep (out-lists of at most 64 ids, any d):
+// vertex p at every alpha of a sweep, for out-lists of at most 96 ids and any
+// d.  The candidate rows are streamed once, 32 dimensions at a time:
 //
-//  a1  read:   lane t holds the t-th listed id.
-//  a3  p-row:  lane j evaluates the canonical FP64 S(p, j) (sequential fma
-//              chain over k) from its own row -- the exact sort key.
-//  a4  sort:   bitonic sort of (S(p, j) bits, id, slot) over the 64 lanes;
-//              p and repeated ids are dropped.
-//  a2  gather: the rows are staged d-chunk by d-chunk in LDS as FP16
-//              u = (x - x_p) * 2^e (p-centred, power-of-two scaled so that
-//              |u| < 2^14), with coalesced 16-byte loads.
-//  a5  Gram:   G~ = U U^T on v_mfma_f32_32x32x16_f16 (FP32 accumulation),
-//              upper blocks only; S~(i, j) = (S(p,i) + S(p,j)) 2^2e - 2 G~(i, j)
-//              goes to an FP32 LDS tile.  In the centred frame the error of
-//              S~ is bounded by E_j ~ (4 u16 + 2 gamma_d) S(p, j) 2^2e (the
-//              later rank j has the larger S(p, .)).
-//  a6  test:   the pruning condition as defined for float32 data,
-//              fl(num^2 S(i,j)) <= fl(den^2 S(p,j)), is decided from S~ when
-//              S~ lies outside [P_j, K_j], thresholds that include E_j and
-//              the FP64 rounding of both products; pairs inside the band are
-//              recomputed in canonical FP64 from the float32 rows.
-//  a7  greedy: 64-bit survivor masks, all alphas in lockstep (as for uint8).
-//  a8  write:  popcount scatter of the kept ranks, -1 padded.
+//  a1  read:   the listed ids by slot (p itself and -1 padding are empty).
+//  a2  gather: per chunk, coalesced 16-byte loads of the slot rows and of x_p
+//              into an FP32 LDS tile; the next chunk's loads are in flight
+//              while the current one is used.
+//  a3  p-row:  lane j accumulates the canonical FP64 S(p, j) of its slot
+//              (t = (double)a - (double)b, fused multiply-add in ascending k)
+//              across the chunks -- the exact sort key and test operand.
+//  a5  Gram:   in the frame centred on p and scaled by 2^e (so that every
+//              |x_jk - x_pk| 2^e < 2^14; e from per-point max |x_k|), each
+//              FP32 difference v is split as hi + lo, two FP16 values, and
+//              G~ = sum hi hi' + hi lo' + lo hi' runs on
+//              v_mfma_f32_32x32x16_f16; for long rows every chunk starts a
+//              fresh accumulator that is then added to the total, which keeps
+//              the FP32 accumulation error near gamma_{3 * 32} instead of
+//              gamma_{3 d}.  S~(i, j) = (S(p, i) + S(p, j)) 2^2e - 2 G~(i, j)
+//              goes to an FP32 LDS tile in slot order.
+//  a4  sort:   (S(p, j), id) ascending -- the order in which the repeated
+//              argmin of Algorithm 1 visits the candidates (a list already in
+//              that order skips the network); repeated ids are dropped.
+//  a6  test:   fl(num^2 S(i, j)) <= fl(den^2 S(p, j)), the condition on
+//              canonical values, is decided from S~ when S~ lies outside
+//              [P_j, K_j]: thresholds that carry the proven bound
+//              |S~ - S(i, j) 2^2e| <= c1 s + c2 sqrt(s) + c3 (s = S(p, j) 2^2e)
+//              and the FP64 rounding of both products.  Pairs inside the band
+//              are recomputed in canonical FP64 from the float32 rows.
+//  a7  greedy: per alpha a rank mask of survivors; the lowest survivor i is
+//              kept, row i of S~ is compared with each lane's thresholds;
+//              the chains of all alphas advance in lockstep.
+//  a8  write:  kept ranks are scattered to their positions, -1 padded.
 #include "dev_common.h"
 
 namespace rp {
@@ -33,50 +43,37 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 
 namespace {
 
-constexpr int kChunk = 128;                         // dimensions per LDS chunk
-constexpr int kUStride = kChunk * 2 + 16;           // bytes per FP16 row in the chunk
-constexpr int kUBytes = 64 * kUStride;              // 17,408
-constexpr int kSTileBytesF = (32 * 64 + 32 * 32) * 4;  // 12,288
+constexpr int kDC = 32;         // dimensions per streamed chunk
+constexpr int kRowF = kDC + 4;  // floats per LDS chunk row (16-byte aligned rows)
 
-__device__ __forceinline__ uint64_t shfl_u64f(uint64_t v, int src) {
-  int lo = __shfl((int)(uint32_t)v, src, 64);
-  int hi = __shfl((int)(uint32_t)(v >> 32), src, 64);
-  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
-}
+template <int NB>
+struct Shape {
+  static constexpr int MS = 32 * NB;                // candidate slots
+  static constexpr int ROWS = MS + 1;               // + x_p in row MS
+  static constexpr int SEG = (ROWS * 8 + 63) / 64;  // 16-byte loads per lane per chunk
+  static constexpr int NP = NB * (NB + 1) / 2;      // 32 x 32 blocks on and above the diagonal
+  static constexpr int NW = NB > 2 ? 2 : 1;         // 64-bit words of a rank mask
+  static constexpr int TILE_B = ROWS * kRowF * 4;   // chunk tile
+  static constexpr int STILE_B = MS * MS * 4;       // S~ tile (overlays the chunk tile)
+  static constexpr int A_B = TILE_B > STILE_B ? TILE_B : STILE_B;
+  static constexpr int LDS_B = A_B + MS * 4 + MS * 4;
+};
 
-// Ascending bitonic sort of (hi, lo) pairs across the wavefront.
-__device__ __forceinline__ void wave_sort2(uint64_t& hi, uint32_t& lo, int lane) {
-#pragma unroll
-  for (int k = 2; k <= 64; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      int ohl = __shfl_xor((int)(uint32_t)hi, j, 64);
-      int ohh = __shfl_xor((int)(uint32_t)(hi >> 32), j, 64);
-      uint32_t olo = (uint32_t)__shfl_xor((int)lo, j, 64);
-      uint64_t ohi = ((uint64_t)(uint32_t)ohh << 32) | (uint32_t)ohl;
-      bool mine_less = hi < ohi || (hi == ohi && lo < olo);
-      bool up = (lane & k) == 0;
-      bool lower = (lane & j) == 0;
-      bool take_min = lower == up;
-      bool keep_mine = take_min ? mine_less : !mine_less;
-      if (!keep_mine) {
-        hi = ohi;
-        lo = olo;
-      }
-    }
-  }
-}
+struct F32Args {
+  double c1, c2, c3;  // rounding band of S~ (scaled units)
+  int32_t nr;         // outputs per alpha (outputs are alpha-major)
+};
 
 // Next float toward -inf / +inf (finite inputs).
 __device__ __forceinline__ float next_down(float f) {
   if (f == 0.f) return -1.401298464e-45f;
-  int b = __float_as_int(f);
+  const int b = __float_as_int(f);
   return __int_as_float(f > 0.f ? b - 1 : b + 1);
 }
 
 __device__ __forceinline__ float next_up(float f) {
   if (f == 0.f) return 1.401298464e-45f;
-  int b = __float_as_int(f);
+  const int b = __float_as_int(f);
   return __int_as_float(f > 0.f ? b + 1 : b - 1);
 }
 
@@ -93,230 +90,486 @@ __device__ __forceinline__ float f32_up(double x) {
   return f;
 }
 
-template <int NA>
-__global__ __launch_bounds__(64) void prune_f32_kernel(GraphView g, SweepArgs a, double c1,
-                                                       double c2, double c3, DevCounters* ctr) {
+// Canonical FP64 squared distance of two float32 rows in global memory.
+template <bool VEC>
+__device__ __forceinline__ double canon_rows(const float* __restrict__ a,
+                                             const float* __restrict__ b, int d) {
+  double acc = 0.0;
+  int k = 0;
+  if (VEC) {
+    for (; k + 4 <= d; k += 4) {
+      const float4 x = *(const float4*)(a + k);
+      const float4 y = *(const float4*)(b + k);
+      double t = (double)x.x - (double)y.x;
+      acc = __fma_rn(t, t, acc);
+      t = (double)x.y - (double)y.y;
+      acc = __fma_rn(t, t, acc);
+      t = (double)x.z - (double)y.z;
+      acc = __fma_rn(t, t, acc);
+      t = (double)x.w - (double)y.w;
+      acc = __fma_rn(t, t, acc);
+    }
+  }
+  for (; k < d; ++k) {
+    const double t = (double)a[k] - (double)b[k];
+    acc = __fma_rn(t, t, acc);
+  }
+  return acc;
+}
+
+__device__ __forceinline__ bool key_less(uint64_t ah, uint32_t al, uint64_t bh, uint32_t bl) {
+  return ah < bh || (ah == bh && al < bl);
+}
+
+// Sort of up to 128 (hi, lo) keys held two per lane (a: ranks 0..63 after the
+// call, b: ranks 64..127): each half is sorted, b is reversed so a ++ b is
+// bitonic, a half-cleaner splits the 64 smallest from the rest, and each half
+// is merged.
+__device__ __forceinline__ void wave_sort128(uint64_t& ah, uint32_t& al, uint64_t& bh,
+                                             uint32_t& bl, int lane) {
+  wave_sort2(ah, al, lane);
+  wave_sort2(bh, bl, lane);
+  const uint64_t rh = shfl_u64(bh, 63 - lane);
+  const uint32_t rl = (uint32_t)__shfl((int)bl, 63 - lane, 64);
+  if (key_less(rh, rl, ah, al)) {
+    bh = ah;
+    bl = al;
+    ah = rh;
+    al = rl;
+  } else {
+    bh = rh;
+    bl = rl;
+  }
+  bitonic_step2<64, 32>(ah, al, lane);
+  bitonic_step2<64, 16>(ah, al, lane);
+  bitonic_step2<64, 8>(ah, al, lane);
+  bitonic_step2<64, 4>(ah, al, lane);
+  bitonic_step2<64, 2>(ah, al, lane);
+  bitonic_step2<64, 1>(ah, al, lane);
+  bitonic_step2<64, 32>(bh, bl, lane);
+  bitonic_step2<64, 16>(bh, bl, lane);
+  bitonic_step2<64, 8>(bh, bl, lane);
+  bitonic_step2<64, 4>(bh, bl, lane);
+  bitonic_step2<64, 2>(bh, bl, lane);
+  bitonic_step2<64, 1>(bh, bl, lane);
+}
+
+__device__ __forceinline__ int ff1_u64(uint64_t v) {
+  const uint64_t u = uniform_u64(v);
+  int i;
+  asm("s_ff1_i32_b64 %0, %1" : "=s"(i) : "s"(u));
+  return i;  // -1 for an empty mask
+}
+
+template <int NA, int NB, bool CSUM, bool VEC>
+__global__ __launch_bounds__(64) void prune_f32_kernel(GraphView g, SweepArgs a, F32Args fa,
+                                                       DevCounters* ctr) {
+  using SH = Shape<NB>;
+  constexpr int MS = SH::MS;
+  constexpr int NW = SH::NW;
+  constexpr int NP = SH::NP;
   extern __shared__ __align__(16) uint8_t lds[];
+  float* T = (float*)lds;                   // chunk tile, ROWS x kRowF
+  float* St = (float*)lds;                  // S~ tile, MS x MS, slot order (after the Gram)
+  float* sr = (float*)(lds + SH::A_B);      // S(p, slot) 2^2e in FP32
+  int32_t* idl = (int32_t*)(sr + MS);       // id by slot, -1 if empty
+
   const int lane = threadIdx.x;
+  const int l32 = lane & 31;
+  const int half = lane >> 5;
   const int64_t p = blockIdx.x;
   const int d = g.d;
   const float* X = (const float*)g.X;
-  uint8_t* Ubytes = lds;                              // FP16 chunk tile
-  float* Stile = (float*)lds;                         // overlays the chunk tile after the Gram
-  const int tile_bytes = kUBytes > kSTileBytesF ? kUBytes : kSTileBytesF;
-  float* xp = (float*)(lds + tile_bytes);             // x_p chunk (kChunk floats)
-  float* sr = xp + kChunk;                            // S(p, .) * 2^2e by rank (FP32)
-  int32_t* idl = (int32_t*)(sr + 64);                 // listed ids by slot
 
   // ---- a1 ------------------------------------------------------------------
   const int m = g.deg[p];
-  const int id = lane < m ? g.nbr[p * g.r_max + lane] : -1;
-  idl[lane] = id;
-
-  // ---- a3: canonical FP64 S(p, j) -----------------------------------------
-  const float* xprow = X + p * d;
-  double s = 0.0;
-  if (id >= 0 && id != (int)p) s = canon_sq_f32(xprow, X + (int64_t)id * d, d);
-
-  // ---- a4: sort by (S(p, j), id) ---------------------------------------------
-  const bool listed = id >= 0 && id != (int)p;
-  uint64_t khi = listed ? (uint64_t)__double_as_longlong(s) : ~0ull;
-  uint32_t klo = listed ? (((uint32_t)id << 6) | (uint32_t)lane) : ~0u;
-  wave_sort2(khi, klo, lane);
-  {
-    uint64_t phi = shfl_u64f(khi, lane > 0 ? lane - 1 : 0);
-    uint32_t plo = (uint32_t)__shfl((int)klo, lane > 0 ? lane - 1 : 0, 64);
-    bool dup = lane > 0 && khi != ~0ull && khi == phi && (klo >> 6) == (plo >> 6);
-    if (dup) khi = ~0ull - 1;
+  int idw[NW];
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const int s = lane + 64 * w;
+    int id = -1;
+    if (s < MS && s < m) id = g.nbr[p * g.r_max + s];
+    if (id == (int)p) id = -1;
+    idw[w] = id;
+    if (s < MS) idl[s] = id;
   }
-  const bool valid = khi < ~0ull - 1;
-  const uint64_t valid_mask = __ballot(valid);
-  const int slot = (int)(klo & 63);
-  const double s_rank = valid ? __longlong_as_double((long long)khi) : 0.0;
-  const int id_rank = valid ? (int)(klo >> 6) : -1;
 
-  // power-of-two scale: |u_k| <= |u| = sqrt(S(p, j)) <= sqrt(max S) -> < 2^14
-  double smax = s_rank;
-  for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_xor(smax, off, 64));
+  // power-of-two scale: |x_jk - x_pk| <= max|x_j| + max|x_p| < 2^ex, e = 14 - ex
+  float mj = 0.f;
+#pragma unroll
+  for (int w = 0; w < NW; ++w)
+    if (idw[w] >= 0) mj = fmaxf(mj, g.maxabs[idw[w]]);
+  for (int off = 32; off > 0; off >>= 1) mj = fmaxf(mj, __shfl_xor(mj, off, 64));
+  const float bound = mj + g.maxabs[p];
   int e = 0;
-  if (smax > 0.0) {
+  if (bound > 0.f) {
     int ex;
-    frexp(sqrt(smax), &ex);  // sqrt(smax) < 2^ex
-    e = 14 - ex;
+    frexpf(bound, &ex);
+    e = min(100, max(-100, 14 - ex));
   }
+  const float scf = ldexpf(1.f, e);
   const double sc = ldexp(1.0, e);
   const double sc2 = sc * sc;
-  sr[lane] = (float)(s_rank * sc2);
-
-  // ---- a2 + a5: chunked gather into FP16 and MFMA ----------------------------
-  const int l32 = lane & 31;
-  const int half = lane >> 5;
-  const int sl0 = __shfl(slot, l32, 64);
-  const int sl1 = __shfl(slot, 32 + l32, 64);
-  v16f acc00 = {0}, acc01 = {0}, acc11 = {0};
-  const float scf = (float)sc;
-  for (int c0 = 0; c0 < d; c0 += kChunk) {
-    const int dc = min(kChunk, d - c0);
-    __syncthreads();  // previous chunk's MFMA reads are done
-    for (int k = lane; k < dc; k += 64) xp[k] = xprow[c0 + k];
-    __syncthreads();
-    // 4 floats (16 B) per lane per load; rows by slot
-    const int q4 = (dc + 3) >> 2;
-    for (int c = lane; c < 64 * q4; c += 64) {
-      const int row = c / q4;
-      const int col = (c - row * q4) * 4;
-      const int rid = idl[row];
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (rid >= 0) {
-        const float* src = X + (int64_t)rid * d + c0 + col;
-        if (col + 4 <= dc && ((((uintptr_t)src) & 15) == 0)) {
-          v = *(const float4*)src;
-        } else {
-          if (col + 0 < dc) v.x = src[0];
-          if (col + 1 < dc) v.y = src[1];
-          if (col + 2 < dc) v.z = src[2];
-          if (col + 3 < dc) v.w = src[3];
-        }
-        v.x = (col + 0 < dc) ? (v.x - xp[col + 0]) * scf : 0.f;
-        v.y = (col + 1 < dc) ? (v.y - xp[col + 1]) * scf : 0.f;
-        v.z = (col + 2 < dc) ? (v.z - xp[col + 2]) * scf : 0.f;
-        v.w = (col + 3 < dc) ? (v.w - xp[col + 3]) * scf : 0.f;
-      }
-      _Float16* dst = (_Float16*)(Ubytes + row * kUStride) + col;
-      dst[0] = (_Float16)v.x;
-      dst[1] = (_Float16)v.y;
-      dst[2] = (_Float16)v.z;
-      dst[3] = (_Float16)v.w;
-    }
-    // zero the padding up to a multiple of 16 dimensions
-    const int dc16 = (dc + 15) & ~15;
-    for (int c = lane; c < 64 * (dc16 - 4 * q4); c += 64) {
-      const int row = c / (dc16 - 4 * q4);
-      const int col = 4 * q4 + (c - row * (dc16 - 4 * q4));
-      ((_Float16*)(Ubytes + row * kUStride))[col] = (_Float16)0.f;
-    }
-    __syncthreads();
-    for (int kk = 0; kk < dc16; kk += 16) {
-      const int off = (kk + half * 8) * 2;
-      v8h f0 = *(const v8h*)(Ubytes + sl0 * kUStride + off);
-      v8h f1 = *(const v8h*)(Ubytes + sl1 * kUStride + off);
-      acc00 = __builtin_amdgcn_mfma_f32_32x32x16_f16(f0, f0, acc00, 0, 0, 0);
-      acc01 = __builtin_amdgcn_mfma_f32_32x32x16_f16(f0, f1, acc01, 0, 0, 0);
-      acc11 = __builtin_amdgcn_mfma_f32_32x32x16_f16(f1, f1, acc11, 0, 0, 0);
-    }
-  }
   __syncthreads();
 
-  // S~ tile (rank order): lane l holds column l % 32 of rows 8(v/4) + 4(l/32) + v%4.
-  {
-    const float scol0 = sr[l32];
-    const float scol1 = sr[32 + l32];
+  // ---- a2 + a3 + a5: streamed chunks ----------------------------------------
+  const int nseg = (m + 1) * 8;   // rows 0..m-1, then x_p; 8 x 16 bytes per row
+  const int nch = (d + kDC - 1) / kDC;
+  const int nbv = (m + 31) >> 5;  // blocks holding listed slots
+  float4 buf[SH::SEG];
+  auto issue = [&](int c0) {
+#pragma unroll
+    for (int t = 0; t < SH::SEG; ++t) {
+      const int c = lane + 64 * t;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (c < nseg) {
+        const int row = c >> 3;
+        const int col = c0 + 4 * (c & 7);
+        const int rid = row < m ? idl[row] : (int)p;
+        if (rid >= 0 && col < d) {
+          const float* src = X + (int64_t)rid * d + col;
+          if (VEC) {
+            v = *(const float4*)src;
+          } else {
+            v.x = src[0];
+            if (col + 1 < d) v.y = src[1];
+            if (col + 2 < d) v.z = src[2];
+            if (col + 3 < d) v.w = src[3];
+          }
+        }
+      }
+      buf[t] = v;
+    }
+  };
+
+  double sp[NW];
+#pragma unroll
+  for (int w = 0; w < NW; ++w) sp[w] = 0.0;
+  v16f cur[NP], tot[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      const int r = 8 * (v >> 2) + 4 * half + (v & 3);
-      const float srow0 = sr[r];
-      const float srow1 = sr[32 + r];
-      Stile[r * 64 + l32] = (srow0 + scol0) - 2.f * acc00[v];
-      Stile[r * 64 + 32 + l32] = (srow0 + scol1) - 2.f * acc01[v];
-      Stile[32 * 64 + r * 32 + l32] = (srow1 + scol1) - 2.f * acc11[v];
+      cur[q][v] = 0.f;
+      tot[q][v] = 0.f;
     }
   }
-  __syncthreads();
 
-  // ---- a6: decision bands per alpha -------------------------------------------
-  // E_j: |S~(i, j) - S(i, j) 2^2e| for every i before j (S(p, i) <= S(p, j)).
-  const double Ej = c1 * s_rank * sc2 + c2 * sqrt(s_rank) * sc + c3;
-  float P[NA], K[NA];
+  issue(0);
+  for (int ch = 0; ch < nch; ++ch) {
+    const int c0 = ch * kDC;
+    const int dc = min(kDC, d - c0);
+    __syncthreads();  // the previous chunk's reads are done
 #pragma unroll
-  for (int ai = 0; ai < NA; ++ai) {
-    const double B = (double)a.den2[ai] * s_rank;      // fl(den^2 S(p, j)), as defined
-    const double t = B / (double)a.num2[ai];
-    const double tlo = t * (1.0 - 0x1p-50);
-    const double thi = t * (1.0 + 0x1p-49);
-    P[ai] = f32_down(tlo * sc2 - Ej);
-    K[ai] = f32_up(thi * sc2 + Ej);
+    for (int t = 0; t < SH::SEG; ++t) {
+      const int c = lane + 64 * t;
+      if (c < nseg) {
+        const int row = c >> 3;
+        const int lrow = row < m ? row : MS;
+        *(float4*)(T + lrow * kRowF + 4 * (c & 7)) = buf[t];
+      }
+    }
+    if (ch + 1 < nch) issue(c0 + kDC);
+    __syncthreads();
+
+    // canonical S(p, j), k ascending
+    const float* xp = T + MS * kRowF;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const int s = lane + 64 * w;
+      if (s < MS) {
+        const float* xj = T + s * kRowF;
+        double acc = sp[w];
+        int k = 0;
+        for (; k + 4 <= dc; k += 4) {
+          const float4 xa = *(const float4*)(xj + k);
+          const float4 xb = *(const float4*)(xp + k);
+          double t = (double)xa.x - (double)xb.x;
+          acc = __fma_rn(t, t, acc);
+          t = (double)xa.y - (double)xb.y;
+          acc = __fma_rn(t, t, acc);
+          t = (double)xa.z - (double)xb.z;
+          acc = __fma_rn(t, t, acc);
+          t = (double)xa.w - (double)xb.w;
+          acc = __fma_rn(t, t, acc);
+        }
+        for (; k < dc; ++k) {
+          const double t = (double)xj[k] - (double)xp[k];
+          acc = __fma_rn(t, t, acc);
+        }
+        sp[w] = acc;
+      }
+    }
+
+    // Gram on MFMA: rows of block b are slots 32 b + l32; lane half h holds
+    // dimensions 8 h .. 8 h + 7 of each 16-wide step.
+#pragma unroll
+    for (int kk = 0; kk < kDC; kk += 16) {
+      if (kk < dc) {
+        const float* pq = xp + kk + 8 * half;
+        const float4 p0 = *(const float4*)pq;
+        const float4 p1 = *(const float4*)(pq + 4);
+        v8h hi[NB], lo[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const float* xr = T + (32 * b + l32) * kRowF + kk + 8 * half;
+          const float4 x0 = *(const float4*)xr;
+          const float4 x1 = *(const float4*)(xr + 4);
+          float u[8];
+          u[0] = (x0.x - p0.x) * scf;
+          u[1] = (x0.y - p0.y) * scf;
+          u[2] = (x0.z - p0.z) * scf;
+          u[3] = (x0.w - p0.w) * scf;
+          u[4] = (x1.x - p1.x) * scf;
+          u[5] = (x1.y - p1.y) * scf;
+          u[6] = (x1.z - p1.z) * scf;
+          u[7] = (x1.w - p1.w) * scf;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const _Float16 h = (_Float16)u[i];
+            hi[b][i] = h;
+            lo[b][i] = (_Float16)(u[i] - (float)h);
+          }
+        }
+        int q = 0;
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi) {
+#pragma unroll
+          for (int bj = bi; bj < NB; ++bj, ++q) {
+            if (bj < nbv) {
+              cur[q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(hi[bi], hi[bj], cur[q], 0, 0, 0);
+              cur[q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(hi[bi], lo[bj], cur[q], 0, 0, 0);
+              cur[q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(lo[bi], hi[bj], cur[q], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+    if (CSUM) {
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          tot[q][v] += cur[q][v];
+          cur[q][v] = 0.f;
+        }
+      }
+    }
   }
 
-  // ---- a7: greedy ----------------------------------------------------------------
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const int s = lane + 64 * w;
+    if (s < MS) sr[s] = (float)(sp[w] * sc2);
+  }
+  __syncthreads();  // every chunk-tile read is done; sr is visible
+
+  // S~ tile in slot order (both triangles; one writer per entry).
+  // Accumulator layout of a 32 x 32 block: lane l holds column l % 32 of rows
+  // 8 (v / 4) + 4 (l / 32) + v % 4 in register v.
+  {
+    int q = 0;
+#pragma unroll
+    for (int bi = 0; bi < NB; ++bi) {
+#pragma unroll
+      for (int bj = bi; bj < NB; ++bj, ++q) {
+        if (bj < nbv) {
+          const int cs = 32 * bj + l32;
+          const float scol = sr[cs];
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int rs = 32 * bi + 8 * (v >> 2) + 4 * half + (v & 3);
+            const float gv = CSUM ? tot[q][v] : cur[q][v];
+            const float val = (sr[rs] + scol) - 2.f * gv;
+            if (bi != bj) {
+              St[rs * MS + cs] = val;
+              St[cs * MS + rs] = val;
+            } else {
+              St[rs * MS + cs] = val;
+            }
+          }
+        }
+      }
+    }
+  }
+
+  // ---- a4: sort by (S(p, j), id); drop repeated ids -------------------------
+  constexpr int kSlotBits = NW == 2 ? 7 : 6;
+  uint64_t kh[2];
+  uint32_t kl[2];
+#pragma unroll
+  for (int w = 0; w < 2; ++w) {
+    kh[w] = ~0ull;
+    kl[w] = ~0u;
+  }
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    if (idw[w] >= 0) {
+      kh[w] = (uint64_t)__double_as_longlong(sp[w]);
+      kl[w] = ((uint32_t)idw[w] << kSlotBits) | (uint32_t)(lane + 64 * w);
+    }
+  }
+  {
+    // a list already in (S, id) order -- every RobustPrune output is -- skips the network
+    bool unsorted = false;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const uint64_t ph = shfl_u64(kh[w], lane > 0 ? lane - 1 : 0);
+      const uint32_t pl = (uint32_t)__shfl((int)kl[w], lane > 0 ? lane - 1 : 0, 64);
+      unsorted = unsorted || (lane > 0 && key_less(kh[w], kl[w], ph, pl));
+    }
+    if (NW == 2) {
+      const uint64_t lh = shfl_u64(kh[0], 63);
+      const uint32_t ll = (uint32_t)__shfl((int)kl[0], 63, 64);
+      unsorted = unsorted || (lane == 0 && key_less(kh[1], kl[1], lh, ll));
+    }
+    if (__ballot(unsorted)) {
+      if (NW == 2) wave_sort128(kh[0], kl[0], kh[1], kl[1], lane);
+      else wave_sort2(kh[0], kl[0], lane);
+    }
+  }
+  uint64_t vm[NW];
+  int slotw[NW], idr[NW];
+  double sw[NW];
+  const uint64_t last0h = shfl_u64(kh[0], 63);
+  const uint32_t last0l = (uint32_t)__shfl((int)kl[0], 63, 64);
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    // previous rank: lane - 1 of this word, or rank 63 for lane 0 of word 1
+    uint64_t ph = shfl_u64(kh[w], lane > 0 ? lane - 1 : 0);
+    uint32_t pl = (uint32_t)__shfl((int)kl[w], lane > 0 ? lane - 1 : 0, 64);
+    if (lane == 0) {
+      ph = w == 0 ? ~0ull - 1 : last0h;
+      pl = w == 0 ? 0u : last0l;
+    }
+    const bool valid = kh[w] != ~0ull &&
+                       !(kh[w] == ph && (kl[w] >> kSlotBits) == (pl >> kSlotBits));
+    vm[w] = __ballot(valid);
+    slotw[w] = valid ? (int)(kl[w] & ((1u << kSlotBits) - 1)) : 0;
+    idr[w] = valid ? (int)(kl[w] >> kSlotBits) : -1;
+    sw[w] = valid ? __longlong_as_double((long long)kh[w]) : 0.0;
+  }
+
+  // ---- a6: decision thresholds of this lane's ranks -------------------------
+  float P[NW][NA], K[NW][NA];
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const double s2 = sw[w] * sc2;
+    const double E = fa.c1 * s2 + fa.c2 * sqrt(s2) + fa.c3;
+#pragma unroll
+    for (int ai = 0; ai < NA; ++ai) {
+      const double B = (double)a.den2[ai] * sw[w];  // fl(den^2 S(p, j)), as defined
+      const double t = B / (double)a.num2[ai];
+      P[w][ai] = f32_down(t * (1.0 - 0x1p-50) * sc2 - E);
+      K[w][ai] = f32_up(t * (1.0 + 0x1p-49) * sc2 + E);
+    }
+  }
+
+  // ---- a7: greedy, all alphas in lockstep ----------------------------------
   int rmax[NA];
 #pragma unroll
-  for (int ai = 0; ai < NA; ++ai) rmax[ai] = 0;
-  for (int o = 0; o < a.n_out; ++o) {
-#pragma unroll
-    for (int ai = 0; ai < NA; ++ai)
-      if (a.out[o].alpha_idx == ai) rmax[ai] = max(rmax[ai], a.out[o].R);
+  for (int ai = 0; ai < NA; ++ai) {
+    rmax[ai] = 0;
+    for (int ir = 0; ir < fa.nr; ++ir) rmax[ai] = max(rmax[ai], a.out[ai * fa.nr + ir].R);
   }
-  uint64_t alive[NA], kept[NA];
-  int cnt[NA], cur[NA];
+  uint64_t alive[NA][NW], kept[NA][NW];
+  int cnt[NA];
 #pragma unroll
   for (int ai = 0; ai < NA; ++ai) {
-    alive[ai] = valid_mask;
-    kept[ai] = 0;
     cnt[ai] = 0;
-    cur[ai] = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      alive[ai][w] = vm[w];
+      kept[ai][w] = 0;
+    }
   }
   unsigned long long rechecks = 0;
-  const int col_hi = 32 * 64 + (lane >= 32 ? lane - 32 : lane);
+
+  auto step = [&](int ai) {
+    int i;
+    bool w1 = false;  // the survivor is in word 1 (ranks 64..127)
+    if (NW == 1) {
+      i = ff1_u64(alive[ai][0]);
+    } else {
+      const int i0 = ff1_u64(alive[ai][0]);
+      const int i1 = ff1_u64(alive[ai][NW - 1]);
+      w1 = i0 < 0;
+      i = w1 ? i1 : i0;
+    }
+    if (i < 0) return;  // chain finished (uniform)
+    const uint64_t bit = 1ull << i;
+    if (w1) {
+      kept[ai][NW - 1] |= bit;
+      alive[ai][NW - 1] &= ~bit;
+    } else {
+      kept[ai][0] |= bit;
+      alive[ai][0] &= ~bit;
+    }
+    if (++cnt[ai] >= rmax[ai]) {  // stop right after the R-th keep
+#pragma unroll
+      for (int w = 0; w < NW; ++w) alive[ai][w] = 0;
+      return;
+    }
+    const int slot_i = w1 ? __builtin_amdgcn_readlane(slotw[NW - 1], i)
+                          : __builtin_amdgcn_readlane(slotw[0], i);
+    const float* srow = St + slot_i * MS;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const float row = srow[slotw[w]];
+      const uint64_t pm = __ballot(row <= P[w][ai]);
+      const uint64_t am = __ballot(row <= K[w][ai]) & ~pm & alive[ai][w];
+      alive[ai][w] &= ~pm;
+      if (am) {
+        const int pid = w1 ? __builtin_amdgcn_readlane(idr[NW - 1], i)
+                           : __builtin_amdgcn_readlane(idr[0], i);
+        bool prune = false;
+        if ((am >> lane) & 1ull) {
+          const double sx = canon_rows<VEC>(X + (int64_t)pid * d, X + (int64_t)idr[w] * d, d);
+          prune = alpha_test_f64(a.num2[ai], a.den2[ai], sx, sw[w]);
+        }
+        alive[ai][w] &= ~(uint64_t)__ballot(prune);
+        rechecks += __popcll(am);
+      }
+    }
+  };
+
   for (;;) {
-    bool any = false;
-    float row[NA];
+    uint64_t any = 0;
 #pragma unroll
     for (int ai = 0; ai < NA; ++ai) {
-      row[ai] = 0.f;
-      if (alive[ai] != 0 && cnt[ai] < rmax[ai]) {
-        const int i = __ffsll((long long)alive[ai]) - 1;
-        kept[ai] |= 1ull << i;
-        alive[ai] &= ~(1ull << i);
-        ++cnt[ai];
-        cur[ai] = i;
-        if (cnt[ai] < rmax[ai] && alive[ai] != 0) {
-          const int addr = i < 32 ? i * 64 + lane : col_hi + (i - 32) * 32;
-          row[ai] = Stile[addr];
-          any = true;
-        } else {
-          alive[ai] = 0;
-        }
-      }
-    }
-    if (!any) break;
 #pragma unroll
-    for (int ai = 0; ai < NA; ++ai) {
-      if (alive[ai] != 0) {
-        const uint64_t pm = __ballot(row[ai] <= P[ai]);
-        const uint64_t am = __ballot(row[ai] > P[ai] && row[ai] <= K[ai]) & alive[ai];
-        alive[ai] &= ~pm;
-        if (am) {
-          // canonical FP64 for the pairs inside the band
-          const int pid = __shfl(id_rank, cur[ai], 64);
-          bool prune = false;
-          if ((am >> lane) & 1ull) {
-            const double sij = canon_sq_f32(X + (int64_t)pid * d, X + (int64_t)id_rank * d, d);
-            prune = alpha_test_f64(a.num2[ai], a.den2[ai], sij, s_rank);
-          }
-          alive[ai] &= ~(uint64_t)__ballot(prune);
-          rechecks += __popcll(am);
-        }
-      }
+      for (int w = 0; w < NW; ++w) any |= alive[ai][w];
     }
+    if (uniform_u64(any) == 0) break;
+#pragma unroll
+    for (int ai = 0; ai < NA; ++ai) step(ai);
   }
 
-  // ---- a8: write -----------------------------------------------------------------
-  for (int o = 0; o < a.n_out; ++o) {
-    const SweepOut& out = a.out[o];
-    uint64_t km = 0;
+  // ---- a8: write every output ------------------------------------------------
+  const uint64_t below = (1ull << lane) - 1ull;
 #pragma unroll
-    for (int ai = 0; ai < NA; ++ai)
-      if (out.alpha_idx == ai) km = kept[ai];
-    const int R = out.R;
-    const int total = __popcll(km);
-    const int cntR = total < R ? total : R;
-    int32_t* orow = out.nbr + p * R;
-    if ((km >> lane) & 1ull) {
-      const int pos = __popcll(km & ((1ull << lane) - 1ull));
-      if (pos < R) orow[pos] = id_rank;
+  for (int ai = 0; ai < NA; ++ai) {
+    int tot_k = 0;
+    int before[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      before[w] = tot_k;
+      tot_k += __popcll(kept[ai][w]);
     }
-    for (int t = cntR + lane; t < R; t += 64) orow[t] = -1;
-    if (lane == 0) out.deg[p] = cntR;
+    for (int ir = 0; ir < fa.nr; ++ir) {
+      const SweepOut& out = a.out[ai * fa.nr + ir];
+      const int R = out.R;
+      const int cntR = tot_k < R ? tot_k : R;
+      int32_t* orow = out.nbr + p * R;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const uint64_t km = kept[ai][w];
+        const int pos = before[w] + __popcll(km & below);
+        if (((km >> lane) & 1ull) && pos < R) orow[pos] = idr[w];
+      }
+      for (int t = cntR + lane; t < R; t += 64) orow[t] = -1;
+      if (lane == 0) out.deg[p] = cntR;
+    }
   }
   if (lane == 0 && rechecks) atomicAdd(&ctr->rechecks, rechecks);
 }
@@ -324,40 +577,50 @@ __global__ __launch_bounds__(64) void prune_f32_kernel(GraphView g, SweepArgs a,
 }  // namespace
 
 bool prune_f32_supported(const GraphView& g) {
-  return g.dtype == RP_F32 && g.r_max <= 64 && g.n <= (1ll << 26);
+  return g.dtype == RP_F32 && g.r_max <= 96 && g.n <= (1ll << 25) && g.maxabs != nullptr;
 }
 
-// Bound constants of |S~ - S 2^2e| <= c1 S(p, j) 2^2e + c2 sqrt(S(p, j)) 2^e + c3
-// for every rank i before j (so S(p, i) <= S(p, j)):
-//   eps   = 2^-11 + 2^-23: rounding of u = (x - x_p) 2^e to FP16 after the FP32
-//           subtraction (relative);
-//   eps_a = 2^-14: absolute error of an FP16 element near zero, even if the
-//           matrix unit flushes subnormal inputs;
-//   gamma = gamma_{d+2} (FP32 accumulation of the exact FP16 products);
-//   |G~ - G| <= (2 eps + gamma) |u_i||u_j| + eps_a sqrt(d) (|u_i| + |u_j|) + d eps_a^2,
-//   and forming S~ = (S(p,i) + S(p,j)) 2^2e - 2 G~ in FP32 adds 8 * 2^-24 S(p,j) 2^2e.
+// Bound of |S~ - S(i, j) 2^2e| for every rank i before j (S(p, i) <= S(p, j)),
+// s = S(p, j) 2^2e, U = (x - x_p) 2^e exact:
+//   e1 = 2^-22 + 2^-23  relative error of hi + lo against U (FP32 subtraction
+//                       2^-24, rounding of lo 2^-22);
+//   ea = 2^-14          absolute error of one element whose hi or lo is an
+//                       FP16 subnormal, even if the matrix unit flushes it;
+//   dropped lo lo'      <= 2^-22 (1 + 2^-9) s;
+//   FP32 accumulation   gamma over the additions into one accumulator, with
+//                       unit 2^-23 (covers truncating hardware), plus the
+//                       gamma of the chunk sums (unit 2^-24);
+//   |G~ - G| <= (2 e1 + e1^2 + lo lo' + acc) s + 2 ea sqrt(d) (1 + e1)(1 + acc) sqrt(s)
+//               + d ea^2 (1 + acc);
+//   S~ = (S(p,i) + S(p,j)) 2^2e - 2 G~ in FP32 adds 8 * 2^-24 s, and the
+//   canonical FP64 values differ from the exact ones by at most 12 d 2^-53 s.
 // Every coefficient is doubled; the FP64 threshold's own rounding is covered
-// separately by the (1 -/+ 2^-50) factors.
-static void f32_bound_constants(int d, double* c1, double* c2, double* c3) {
-  const double eps = 0x1p-11 + 0x1p-23;
-  const double eps_a = 0x1p-14;
-  const double u32 = 0x1p-24;
-  const double g = (d + 2) * u32 / (1.0 - (d + 2) * u32);
-  *c1 = 2.0 * (4.0 * eps + 2.0 * g * (1.0 + eps) * (1.0 + eps) + 8.0 * u32);
-  *c2 = 2.0 * 4.0 * eps_a * (1.0 + eps) * (1.0 + g) * sqrt((double)d);
-  *c3 = 2.0 * 2.0 * d * eps_a * eps_a * (1.0 + g);
+// by the (1 -/+ 2^-50) factors.
+static void f32_bound_constants(int d, bool csum, double* c1, double* c2, double* c3) {
+  auto gam = [](double n, double u) { return n * u / (1.0 - n * u); };
+  const double u24 = 0x1p-24;
+  const double e1 = 0x1p-22 + 0x1p-23;
+  const double ea = 0x1p-14;
+  const double nadd = csum ? 3.0 * kDC + 1.0 : 3.0 * d + 1.0;
+  const double g1 = gam(nadd, 0x1p-23);
+  const double g2 = csum ? gam((double)((d + kDC - 1) / kDC), u24) : 0.0;
+  const double acc = (g1 + g2 + g1 * g2) * (1.0 + 0x1p-9);
+  const double lolo = 0x1p-22 * (1.0 + 0x1p-9);
+  const double sd = sqrt((double)d);
+  *c1 = 2.0 * (2.0 * (2.0 * e1 + e1 * e1 + lolo + acc) + 8.0 * u24 + 12.0 * d * 0x1p-53);
+  *c2 = 2.0 * (2.0 * 2.0 * ea * sd * (1.0 + e1) * (1.0 + acc));
+  *c3 = 2.0 * (2.0 * d * ea * ea * (1.0 + acc));
 }
 
-hipError_t launch_prune_f32(const GraphView& g, const SweepArgs& a, DevCounters* ctr,
-                            hipStream_t s) {
-  double c1, c2, c3;
-  f32_bound_constants(g.d, &c1, &c2, &c3);
-  const int tile = kUBytes > kSTileBytesF ? kUBytes : kSTileBytesF;
-  const size_t shmem = (size_t)tile + kChunk * 4 + 64 * 4 + 64 * 4;
+template <int NB, bool CSUM, bool VEC>
+static hipError_t launch_shape(const GraphView& g, const SweepArgs& a, const F32Args& fa,
+                               DevCounters* ctr, hipStream_t s) {
+  const size_t shmem = Shape<NB>::LDS_B;
   dim3 grid((unsigned)g.n), block(64);
-#define RP_LAUNCH_F32(NA_)                                                                    \
-  case NA_:                                                                                   \
-    hipLaunchKernelGGL(prune_f32_kernel<NA_>, grid, block, shmem, s, g, a, c1, c2, c3, ctr); \
+#define RP_LAUNCH_F32(NA_)                                                                  \
+  case NA_:                                                                                 \
+    hipLaunchKernelGGL((prune_f32_kernel<NA_, NB, CSUM, VEC>), grid, block, shmem, s, g, a, \
+                       fa, ctr);                                                            \
     break;
   switch (a.n_alpha) {
     RP_LAUNCH_F32(1)
@@ -373,6 +636,30 @@ hipError_t launch_prune_f32(const GraphView& g, const SweepArgs& a, DevCounters*
   }
 #undef RP_LAUNCH_F32
   return hipGetLastError();
+}
+
+template <bool VEC>
+static hipError_t launch_vec(const GraphView& g, const SweepArgs& a, F32Args& fa,
+                             DevCounters* ctr, hipStream_t s) {
+  if (g.r_max > 64) {
+    f32_bound_constants(g.d, true, &fa.c1, &fa.c2, &fa.c3);
+    return launch_shape<3, true, VEC>(g, a, fa, ctr, s);
+  }
+  if (g.d > 128) {
+    f32_bound_constants(g.d, true, &fa.c1, &fa.c2, &fa.c3);
+    return launch_shape<2, true, VEC>(g, a, fa, ctr, s);
+  }
+  f32_bound_constants(g.d, false, &fa.c1, &fa.c2, &fa.c3);
+  return launch_shape<2, false, VEC>(g, a, fa, ctr, s);
+}
+
+hipError_t launch_prune_f32(const GraphView& g, const SweepArgs& a, DevCounters* ctr,
+                            hipStream_t s) {
+  if (a.n_alpha < 1 || a.n_out % a.n_alpha != 0) return hipErrorInvalidValue;
+  F32Args fa;
+  fa.nr = a.n_out / a.n_alpha;
+  const bool vec = (g.d % 4) == 0 && (((uintptr_t)g.X) & 15) == 0;
+  return vec ? launch_vec<true>(g, a, fa, ctr, s) : launch_vec<false>(g, a, fa, ctr, s);
 }
 
 }  // namespace rp

@@ -43,6 +43,25 @@ hipError_t launch_norms_u8(const GraphView& g, uint32_t* norms, hipStream_t s) {
   return hipGetLastError();
 }
 
+// max_k |x_k| of every float32 point, for the MFMA scale of a vertex's frame.
+__global__ void maxabs_f32_kernel(const float* __restrict__ X, int64_t n, int d,
+                                  float* __restrict__ maxabs) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const float* x = X + p * d;
+  float acc = 0.f;
+  for (int k = 0; k < d; ++k) acc = fmaxf(acc, fabsf(x[k]));
+  maxabs[p] = acc;
+}
+
+hipError_t launch_maxabs_f32(const GraphView& g, float* maxabs, hipStream_t s) {
+  const int block = 256;
+  const int64_t grid = (g.n + block - 1) / block;
+  hipLaunchKernelGGL(maxabs_f32_kernel, dim3((unsigned)grid), dim3(block), 0, s,
+                     (const float*)g.X, g.n, g.d, maxabs);
+  return hipGetLastError();
+}
+
 hipError_t launch_validate(const GraphView& g, DevCounters* ctr, hipStream_t s) {
   const int block = 256;
   const int64_t grid = (g.n + block - 1) / block;

@@ -14,7 +14,8 @@ struct rp_graph {
   rp_graph* base;  // non-null for derived handles
   int device;
   int64_t nodes;   // vertex-prunes enqueued, counted on the host
-  uint32_t* norms; // owned by a base handle (uint8 points), shared by derived ones
+  void* aux;       // per-point array owned by a base handle, shared by derived ones:
+                   // |x|^2 (uint8 points) or max_k |x_k| (float32 points)
 };
 
 namespace {
@@ -127,9 +128,9 @@ rp_status rp_load_graph(const void* points, int32_t dtype, int64_t n, int32_t d,
     return fail(RP_EINVAL, "points is not a device array of n*d elements");
   rp_graph* g = new (std::nothrow) rp_graph();
   if (!g) return fail(RP_ENOMEM, "host allocation failed");
-  g->view = {points, dtype, n, d, nbr, deg, r_max, start, nullptr};
+  g->view = {points, dtype, n, d, nbr, deg, r_max, start, nullptr, nullptr};
   g->base = nullptr;
-  g->norms = nullptr;
+  g->aux = nullptr;
   if (hipGetDevice(&g->device) != hipSuccess) {
     delete g;
     return fail(RP_EDEVICE, "hipGetDevice failed");
@@ -140,18 +141,23 @@ rp_status rp_load_graph(const void* points, int32_t dtype, int64_t n, int32_t d,
     return fail(RP_ENOMEM, "hipMalloc of counters failed");
   }
   rp_status st = validate_adjacency(g->view, g->ctr, (hipStream_t)stream);
-  if (st == RP_OK && dtype == RP_U8) {
-    if (hipMalloc((void**)&g->norms, (size_t)n * sizeof(uint32_t)) != hipSuccess) {
+  if (st == RP_OK) {
+    if (hipMalloc(&g->aux, (size_t)n * 4) != hipSuccess) {
       (void)hipGetLastError();
-      g->norms = nullptr;
-      st = fail(RP_ENOMEM, "hipMalloc of point norms failed");
+      g->aux = nullptr;
+      st = fail(RP_ENOMEM, "hipMalloc of the per-point array failed");
+    } else if (dtype == RP_U8) {
+      g->view.norms = (const uint32_t*)g->aux;
+      st = check_launch(rp::launch_norms_u8(g->view, (uint32_t*)g->aux, (hipStream_t)stream),
+                        "norms");
     } else {
-      g->view.norms = g->norms;
-      st = check_launch(rp::launch_norms_u8(g->view, g->norms, (hipStream_t)stream), "norms");
+      g->view.maxabs = (const float*)g->aux;
+      st = check_launch(rp::launch_maxabs_f32(g->view, (float*)g->aux, (hipStream_t)stream),
+                        "maxabs");
     }
   }
   if (st != RP_OK) {
-    if (g->norms) (void)hipFree(g->norms);
+    if (g->aux) (void)hipFree(g->aux);
     (void)hipFree(g->ctr);
     delete g;
     return st;
@@ -175,7 +181,7 @@ rp_status rp_graph_derive(rp_graph_t base, const int32_t* nbr, const int32_t* de
   g->view.r_max = r_max;
   g->base = base;
   g->device = base->device;
-  g->norms = nullptr;  // view.norms points at the base's array
+  g->aux = nullptr;  // the view points at the base's per-point array
   if (hipMalloc((void**)&g->ctr, sizeof(rp::DevCounters)) != hipSuccess) {
     (void)hipGetLastError();
     delete g;
@@ -290,7 +296,7 @@ void rp_free_graph(rp_graph_t g) {
   if (!g) return;
   (void)hipDeviceSynchronize();
   (void)hipFree(g->ctr);
-  if (g->norms) (void)hipFree(g->norms);
+  if (g->aux) (void)hipFree(g->aux);
   delete g;
 }
 

@@ -49,11 +49,13 @@ struct GraphView {
   int32_t r_max;
   int32_t start;
   const uint32_t* norms;  // |x|^2 per point (uint8 points; library-owned), else null
+  const float* maxabs;    // max_k |x_k| per point (float32 points; library-owned), else null
 };
 
 // Kernel launchers (each returns hipGetLastError() of its launch).
 hipError_t launch_validate(const GraphView& g, DevCounters* ctr, hipStream_t s);
 hipError_t launch_norms_u8(const GraphView& g, uint32_t* norms, hipStream_t s);
+hipError_t launch_maxabs_f32(const GraphView& g, float* maxabs, hipStream_t s);
 hipError_t launch_prune_plain(const GraphView& g, uint32_t num2, uint32_t den2, int32_t R,
                               int32_t* out_nbr, int32_t* out_deg, DevCounters* ctr,
                               hipStream_t s);

@@ -148,6 +148,36 @@ def test_gist_f32_chunked_dimension():
     _sampled_sweep_check(w, w.X, o_nbr, o_deg, outs, alphas, Rs, w.sample[:600])
 
 
+def test_gist_f32_ninety_six_candidates():
+    """GIST-1M recipe at reduced n: d = 960, exact 192-NN, base RobustPrune at
+    6/5 with R = 96, then the sweep {11/10, 1} x R {96, 64, 32} through the
+    96-candidate kernel (chunk sums of the split-FP16 Gram).  The oracle
+    recomputes 250 sampled vertices (base rows and every output); the plain
+    kernel agrees on all vertices."""
+    dev = _dev()
+    w = workloads.build("gist_f32", n=2500, nq=10, device=dev)
+    spec = w.spec
+    n = w.X.shape[0]
+    nodes = w.sample[:250]
+    s_nbr, s_deg, _ = oracle.prune_graph(w.X, w.knn, w.knn_deg, *spec.base_alpha, spec.base_R,
+                                         nodes=nodes)
+    g0 = _graph(w.X, w.knn, w.knn_deg, w.start)
+    nb, dg = g0.prune(spec.base_alpha, spec.base_R)
+    assert np.array_equal(_np(nb)[nodes], s_nbr)
+    assert np.array_equal(_np(dg)[nodes], s_deg)
+    o_nbr = np.zeros((n, spec.base_R), np.int32)
+    o_deg = np.zeros(n, np.int32)
+    o_nbr[nodes], o_deg[nodes] = s_nbr, s_deg
+    g = g0.derive(nb, dg)
+    g.counters(reset=True)
+    outs = g.prune_sweep(spec.sweep, spec.Rs)
+    _sampled_sweep_check(w, w.X, o_nbr, o_deg, outs, spec.sweep, spec.Rs, nodes)
+    nr = len(spec.Rs)
+    for o, (b_nb, b_dg) in enumerate(outs):
+        p_nb, p_dg = g.prune_plain(spec.sweep[o // nr], spec.Rs[o % nr])
+        assert torch.equal(p_nb, b_nb) and torch.equal(p_dg, b_dg)
+
+
 def test_tiny_search_matches_oracle(tiny):
     w, spec = tiny, tiny.spec
     o_nbr, o_deg = _oracle_base(w)
@@ -248,22 +278,26 @@ def test_edge_cases_u8_batched_kernel(d, r_max):
             assert np.array_equal(_np(dg), e_deg), (a, R)
 
 
-@pytest.mark.parametrize("d", [5, 32, 100])
-def test_edge_cases_f32_batched_kernel(d):
-    """float32 shapes that take the FP16-MFMA kernel: exact ties (values on a
-    1/4 grid make many alpha tests land exactly on the threshold and go to the
-    FP64 recheck), duplicate points, ragged and empty lists, wide dynamic range."""
-    rng = np.random.default_rng(d)
+@pytest.mark.parametrize("r_max", [64, 96])
+@pytest.mark.parametrize("d", [5, 32, 100, 300])
+def test_edge_cases_f32_batched_kernel(d, r_max):
+    """float32 shapes that take the split-FP16 MFMA kernel (up to 64 and up to
+    96 candidates, d with and without a ragged 32-wide chunk, rows that are
+    not 16-byte multiples): exact ties (values on a 1/4 grid make many alpha
+    tests land exactly on the threshold and go to the FP64 recheck), duplicate
+    points, ragged and empty lists, wide dynamic range."""
+    rng = np.random.default_rng(d + r_max)
     n = 400
     X = (rng.integers(-3, 4, (n, d)) * 0.25).astype(np.float32)
     X[50:60] = (rng.standard_normal((10, d)) * 1e6).astype(np.float32)
     X[60:70] = (rng.standard_normal((10, d)) * 1e-6).astype(np.float32)
     X[10:15] = X[7]
-    nbr = rng.integers(0, n, (n, 64)).astype(np.int32)
+    nbr = rng.integers(0, n, (n, r_max)).astype(np.int32)
     nbr[:, 3] = np.arange(n)
     nbr[7, :20] = np.arange(10, 30)
-    deg = rng.integers(0, 65, n).astype(np.int32)
+    deg = rng.integers(0, r_max + 1, n).astype(np.int32)
     deg[:2] = 0
+    deg[2:6] = r_max
     g = _graph(X, nbr, deg, 0)
     alphas = [(1, 1), (21, 20), (6, 5), (3, 2), (2, 1)]
     Rs = [64, 7]
