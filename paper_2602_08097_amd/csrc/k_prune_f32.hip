@@ -54,7 +54,8 @@ struct Shape {
   static constexpr int NP = NB * (NB + 1) / 2;      // 32 x 32 blocks on and above the diagonal
   static constexpr int NW = NB > 2 ? 2 : 1;         // 64-bit words of a rank mask
   static constexpr int TILE_B = ROWS * kRowF * 4;   // chunk tile
-  static constexpr int STILE_B = MS * MS * 4;       // S~ tile (overlays the chunk tile)
+  static constexpr int SP = MS + 4;                 // S~ row stride (16-byte rows, conflict-free scans)
+  static constexpr int STILE_B = MS * SP * 4;       // S~ tile (overlays the chunk tile)
   static constexpr int A_B = TILE_B > STILE_B ? TILE_B : STILE_B;
   static constexpr int LDS_B = A_B + MS * 4 + MS * 4;
 };
@@ -168,9 +169,10 @@ __global__ __launch_bounds__(64) void prune_f32_kernel(GraphView g, SweepArgs a,
   constexpr int MS = SH::MS;
   constexpr int NW = SH::NW;
   constexpr int NP = SH::NP;
+  constexpr int SP = SH::SP;
   extern __shared__ __align__(16) uint8_t lds[];
   float* T = (float*)lds;                   // chunk tile, ROWS x kRowF
-  float* St = (float*)lds;                  // S~ tile, MS x MS, slot order (after the Gram)
+  float* St = (float*)lds;                  // S~ tile, MS x SP, slot order (after the Gram)
   float* sr = (float*)(lds + SH::A_B);      // S(p, slot) 2^2e in FP32
   int32_t* idl = (int32_t*)(sr + MS);       // id by slot, -1 if empty
 
@@ -312,6 +314,7 @@ __global__ __launch_bounds__(64) void prune_f32_kernel(GraphView g, SweepArgs a,
         v8h hi[NB], lo[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
+          if (b >= nbv) break;  // uniform
           const float* xr = T + (32 * b + l32) * kRowF + kk + 8 * half;
           const float4 x0 = *(const float4*)xr;
           const float4 x1 = *(const float4*)(xr + 4);
@@ -382,10 +385,10 @@ __global__ __launch_bounds__(64) void prune_f32_kernel(GraphView g, SweepArgs a,
             const float gv = CSUM ? tot[q][v] : cur[q][v];
             const float val = (sr[rs] + scol) - 2.f * gv;
             if (bi != bj) {
-              St[rs * MS + cs] = val;
-              St[cs * MS + rs] = val;
+              St[rs * SP + cs] = val;
+              St[cs * SP + rs] = val;
             } else {
-              St[rs * MS + cs] = val;
+              St[rs * SP + cs] = val;
             }
           }
         }
@@ -409,6 +412,7 @@ __global__ __launch_bounds__(64) void prune_f32_kernel(GraphView g, SweepArgs a,
       kl[w] = ((uint32_t)idw[w] << kSlotBits) | (uint32_t)(lane + 64 * w);
     }
   }
+  bool sorted;  // slot order is rank order
   {
     // a list already in (S, id) order -- every RobustPrune output is -- skips the network
     bool unsorted = false;
@@ -423,7 +427,8 @@ __global__ __launch_bounds__(64) void prune_f32_kernel(GraphView g, SweepArgs a,
       const uint32_t ll = (uint32_t)__shfl((int)kl[0], 63, 64);
       unsorted = unsorted || (lane == 0 && key_less(kh[1], kl[1], lh, ll));
     }
-    if (__ballot(unsorted)) {
+    sorted = __ballot(unsorted) == 0;
+    if (!sorted) {
       if (NW == 2) wave_sort128(kh[0], kl[0], kh[1], kl[1], lane);
       else wave_sort2(kh[0], kl[0], lane);
     }
@@ -458,8 +463,10 @@ __global__ __launch_bounds__(64) void prune_f32_kernel(GraphView g, SweepArgs a,
     const double E = fa.c1 * s2 + fa.c2 * sqrt(s2) + fa.c3;
 #pragma unroll
     for (int ai = 0; ai < NA; ++ai) {
-      const double B = (double)a.den2[ai] * sw[w];  // fl(den^2 S(p, j)), as defined
-      const double t = B / (double)a.num2[ai];
+      // t = fl(S(p, j) fl(den^2 / num^2)) is within 2^-51.4 of den^2 S(p, j) / num^2,
+      // so S(i, j) <= t (1 - 2^-50) implies fl(num^2 S(i, j)) <= fl(den^2 S(p, j)),
+      // and S(i, j) > t (1 + 2^-49) implies the opposite.
+      const double t = sw[w] * a.ratio[ai];
       P[w][ai] = f32_down(t * (1.0 - 0x1p-50) * sc2 - E);
       K[w][ai] = f32_up(t * (1.0 + 0x1p-49) * sc2 + E);
     }
@@ -485,54 +492,115 @@ __global__ __launch_bounds__(64) void prune_f32_kernel(GraphView g, SweepArgs a,
   }
   unsigned long long rechecks = 0;
 
-  auto step = [&](int ai) {
-    int i;
-    bool w1 = false;  // the survivor is in word 1 (ranks 64..127)
-    if (NW == 1) {
-      i = ff1_u64(alive[ai][0]);
-    } else {
-      const int i0 = ff1_u64(alive[ai][0]);
-      const int i1 = ff1_u64(alive[ai][NW - 1]);
-      w1 = i0 < 0;
-      i = w1 ? i1 : i0;
-    }
-    if (i < 0) return;  // chain finished (uniform)
-    const uint64_t bit = 1ull << i;
-    if (w1) {
-      kept[ai][NW - 1] |= bit;
-      alive[ai][NW - 1] &= ~bit;
-    } else {
-      kept[ai][0] |= bit;
-      alive[ai][0] &= ~bit;
-    }
-    if (++cnt[ai] >= rmax[ai]) {  // stop right after the R-th keep
+  if constexpr (NW == 1) {
+    // Rows that can prune.  For a list in rank order, row i can remove some
+    // j > i at alpha_k only if S~(i, j) <= K_k(j) for some j, which implies
+    // fl(S~(i, j) / s_j) <= kappa_k := max_j fl(K_k(j) / s_j) (FP32 products
+    // with the same reciprocal, so the implication survives rounding).  A
+    // survivor whose row cannot prune is kept with nothing removed, so the
+    // greedy below keeps whole runs of such survivors at once and only reads
+    // the rows that can prune.  Lists out of rank order visit every row.
+    uint64_t vis[NA];
+    if (sorted) {
+      const bool v0 = (vm[0] >> lane) & 1ull;
+      const double s2 = sw[0] * sc2;
+      // 1 / s_j by rank (NaN for empty ranks, whose products are then ignored)
+      const float inv = v0 ? (s2 > 0.0 ? (float)(1.0 / s2) : 0.f) : __builtin_nanf("");
+      float* invt = sr;  // S(p, .) by slot is no longer needed
+      invt[lane] = inv;
+      __syncthreads();
+      float zmin = __builtin_inff();
+      const float* myrow = St + lane * SP;
+#pragma unroll 4
+      for (int j0 = 0; j0 < MS; j0 += 4) {
+        const float4 v = *(const float4*)(myrow + j0);
+        const float4 iv = *(const float4*)(invt + j0);
+        const float z0 = v.x * iv.x, z1 = v.y * iv.y, z2 = v.z * iv.z, z3 = v.w * iv.w;
+        zmin = fminf(zmin, j0 + 0 > lane ? z0 : __builtin_inff());
+        zmin = fminf(zmin, j0 + 1 > lane ? z1 : __builtin_inff());
+        zmin = fminf(zmin, j0 + 2 > lane ? z2 : __builtin_inff());
+        zmin = fminf(zmin, j0 + 3 > lane ? z3 : __builtin_inff());
+      }
 #pragma unroll
-      for (int w = 0; w < NW; ++w) alive[ai][w] = 0;
-      return;
-    }
-    const int slot_i = w1 ? __builtin_amdgcn_readlane(slotw[NW - 1], i)
-                          : __builtin_amdgcn_readlane(slotw[0], i);
-    const float* srow = St + slot_i * MS;
+      for (int ai = 0; ai < NA; ++ai) {
+        float q = v0 ? K[0][ai] * inv : -__builtin_inff();
+        for (int off = 32; off > 0; off >>= 1) q = fmaxf(q, __shfl_xor(q, off, 64));
+        vis[ai] = __ballot(v0 && zmin <= q);
+      }
+    } else {
 #pragma unroll
-    for (int w = 0; w < NW; ++w) {
-      const float row = srow[slotw[w]];
-      const uint64_t pm = __ballot(row <= P[w][ai]);
-      const uint64_t am = __ballot(row <= K[w][ai]) & ~pm & alive[ai][w];
-      alive[ai][w] &= ~pm;
-      if (am) {
-        const int pid = w1 ? __builtin_amdgcn_readlane(idr[NW - 1], i)
-                           : __builtin_amdgcn_readlane(idr[0], i);
-        bool prune = false;
-        if ((am >> lane) & 1ull) {
-          const double sx = canon_rows<VEC>(X + (int64_t)pid * d, X + (int64_t)idr[w] * d, d);
-          prune = alpha_test_f64(a.num2[ai], a.den2[ai], sx, sw[w]);
+      for (int ai = 0; ai < NA; ++ai) vis[ai] = vm[0];
+    }
+
+    // Per chain: the survivors before the first survivor i whose row can
+    // prune are kept in turn (none removes anything), then i is kept and its
+    // row decides the rest; a chain stops at its largest R (trimmed below).
+    // Alphas arrive in descending order, so chains visit ever more rows and
+    // usually finish in index order: phase s0 advances chains s0..NA-1 while
+    // chain s0 has survivors (a finished chain repeats harmless steps).
+#pragma unroll
+    for (int s0 = 0; s0 < NA; ++s0) {
+    while (uniform_u64(alive[s0][0]) != 0) {
+      float row[NA];
+      int istar[NA];
+#pragma unroll
+      for (int ai = s0; ai < NA; ++ai) {
+        const uint64_t al = uniform_u64(alive[ai][0]);
+        int i = ff1_u64(al & vis[ai]);
+        const uint64_t upto = i < 0 ? ~0ull : (2ull << i) - 1ull;  // ranks <= i
+        const uint64_t batch = al & upto;
+        const uint64_t k = uniform_u64(kept[ai][0]) | batch;
+        kept[ai][0] = k;
+        alive[ai][0] = (i < 0 || __popcll(k) >= rmax[ai]) ? 0ull : al & ~batch;
+        i = max(i, 0);
+        istar[ai] = i;
+        const int slot_i = __builtin_amdgcn_readlane(slotw[0], i);
+        row[ai] = St[slot_i * SP + slotw[0]];
+      }
+      uint64_t amb[NA];
+      uint64_t any_amb = 0;
+#pragma unroll
+      for (int ai = s0; ai < NA; ++ai) {
+        const uint64_t pm = __ballot(row[ai] <= P[0][ai]);
+        amb[ai] = __ballot(row[ai] <= K[0][ai]) & ~pm & alive[ai][0];
+        alive[ai][0] &= ~pm;
+        any_amb |= amb[ai];
+      }
+      if (uniform_u64(any_amb) != 0) {
+#pragma unroll
+        for (int ai = s0; ai < NA; ++ai) {
+          const uint64_t am = uniform_u64(amb[ai]);
+          if (am) {
+            const int pid = __builtin_amdgcn_readlane(idr[0], istar[ai]);
+            bool prune = false;
+            if ((am >> lane) & 1ull) {
+              const double sx =
+                  canon_rows<VEC>(X + (int64_t)pid * d, X + (int64_t)idr[0] * d, d);
+              prune = alpha_test_f64(a.num2[ai], a.den2[ai], sx, sw[0]);
+            }
+            alive[ai][0] &= ~(uint64_t)__ballot(prune);
+            rechecks += __popcll(am);
+          }
         }
-        alive[ai][w] &= ~(uint64_t)__ballot(prune);
-        rechecks += __popcll(am);
       }
     }
-  };
-
+    }
+    // a chain that reached its R keeps its first R ranks
+#pragma unroll
+    for (int ai = 0; ai < NA; ++ai) {
+      const uint64_t k = kept[ai][0];
+      if (__popcll(k) > rmax[ai]) {
+        const int before = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(k >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)k, 0u));
+        kept[ai][0] = __ballot(((k >> lane) & 1ull) && before < rmax[ai]);
+      }
+    }
+  } else {
+  // One lockstep step advances every chain: keep its lowest survivor i, read
+  // row i of S~ (the reads of all chains are in flight together), decide the
+  // pairs outside the band, then recheck the pairs inside it.  A finished
+  // chain takes i = rank 0, which only re-sets a bit that is already kept or
+  // that the final mask with the valid ranks removes.
   for (;;) {
     uint64_t any = 0;
 #pragma unroll
@@ -541,8 +609,84 @@ __global__ __launch_bounds__(64) void prune_f32_kernel(GraphView g, SweepArgs a,
       for (int w = 0; w < NW; ++w) any |= alive[ai][w];
     }
     if (uniform_u64(any) == 0) break;
+    float row[NA][NW];
+    int istar[NA];
+    bool hiw[NA];  // the survivor is in word 1 (ranks 64..127)
 #pragma unroll
-    for (int ai = 0; ai < NA; ++ai) step(ai);
+    for (int ai = 0; ai < NA; ++ai) {
+      int i;
+      bool w1 = false;
+      if (NW == 1) {
+        i = ff1_u64(alive[ai][0]);
+      } else {
+        const int i0 = ff1_u64(alive[ai][0]);
+        const int i1 = ff1_u64(alive[ai][NW - 1]);
+        w1 = i0 < 0 && i1 >= 0;
+        i = w1 ? i1 : i0;
+      }
+      const bool live = i >= 0;
+      i = max(i, 0);
+      const uint64_t bit = 1ull << i;
+      if (NW == 1) {
+        kept[ai][0] |= bit;
+        alive[ai][0] &= ~bit;
+      } else {
+        kept[ai][0] |= w1 ? 0ull : bit;
+        alive[ai][0] &= w1 ? ~0ull : ~bit;
+        kept[ai][NW - 1] |= w1 ? bit : 0ull;
+        alive[ai][NW - 1] &= w1 ? ~bit : ~0ull;
+      }
+      cnt[ai] += live ? 1 : 0;
+      if (cnt[ai] >= rmax[ai]) {  // stop right after the R-th keep
+#pragma unroll
+        for (int w = 0; w < NW; ++w) alive[ai][w] = 0;
+      }
+      const int slot_i = __builtin_amdgcn_readlane(w1 ? slotw[NW - 1] : slotw[0], i);
+      const float* srow = St + slot_i * SP;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) row[ai][w] = srow[slotw[w]];
+      istar[ai] = i;
+      hiw[ai] = w1;
+    }
+    uint64_t amb[NA][NW];
+    uint64_t any_amb = 0;
+#pragma unroll
+    for (int ai = 0; ai < NA; ++ai) {
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const uint64_t pm = __ballot(row[ai][w] <= P[w][ai]);
+        amb[ai][w] = __ballot(row[ai][w] <= K[w][ai]) & ~pm & alive[ai][w];
+        alive[ai][w] &= ~pm;
+        any_amb |= amb[ai][w];
+      }
+    }
+    if (uniform_u64(any_amb) != 0) {
+#pragma unroll
+      for (int ai = 0; ai < NA; ++ai) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          const uint64_t am = uniform_u64(amb[ai][w]);
+          if (am) {
+            const int pid =
+                __builtin_amdgcn_readlane(hiw[ai] ? idr[NW - 1] : idr[0], istar[ai]);
+            bool prune = false;
+            if ((am >> lane) & 1ull) {
+              const double sx =
+                  canon_rows<VEC>(X + (int64_t)pid * d, X + (int64_t)idr[w] * d, d);
+              prune = alpha_test_f64(a.num2[ai], a.den2[ai], sx, sw[w]);
+            }
+            alive[ai][w] &= ~(uint64_t)__ballot(prune);
+            rechecks += __popcll(am);
+          }
+        }
+      }
+    }
+  }
+  }
+#pragma unroll
+  for (int ai = 0; ai < NA; ++ai) {
+#pragma unroll
+    for (int w = 0; w < NW; ++w) kept[ai][w] &= vm[w];
   }
 
   // ---- a8: write every output ------------------------------------------------
@@ -653,11 +797,35 @@ static hipError_t launch_vec(const GraphView& g, const SweepArgs& a, F32Args& fa
   return launch_shape<2, false, VEC>(g, a, fa, ctr, s);
 }
 
-hipError_t launch_prune_f32(const GraphView& g, const SweepArgs& a, DevCounters* ctr,
+hipError_t launch_prune_f32(const GraphView& g, const SweepArgs& a_in, DevCounters* ctr,
                             hipStream_t s) {
-  if (a.n_alpha < 1 || a.n_out % a.n_alpha != 0) return hipErrorInvalidValue;
+  if (a_in.n_alpha < 1 || a_in.n_out % a_in.n_alpha != 0) return hipErrorInvalidValue;
   F32Args fa;
-  fa.nr = a.n_out / a.n_alpha;
+  fa.nr = a_in.n_out / a_in.n_alpha;
+  // the kernel takes the alphas in descending order (num_a den_b vs num_b den_a);
+  // outputs are alpha-major (o = alpha * nr + iR) and move with their alpha
+  SweepArgs a = a_in;
+  int order[kMaxAlphas];
+  for (int i = 0; i < a_in.n_alpha; ++i) order[i] = i;
+  for (int i = 1; i < a_in.n_alpha; ++i) {
+    const int v = order[i];
+    int j = i - 1;
+    while (j >= 0 && (uint64_t)a_in.num2[v] * a_in.den2[order[j]] >
+                         (uint64_t)a_in.num2[order[j]] * a_in.den2[v]) {
+      order[j + 1] = order[j];
+      --j;
+    }
+    order[j + 1] = v;
+  }
+  for (int k = 0; k < a_in.n_alpha; ++k) {
+    a.num2[k] = a_in.num2[order[k]];
+    a.den2[k] = a_in.den2[order[k]];
+    a.ratio[k] = a_in.ratio[order[k]];
+    for (int ir = 0; ir < fa.nr; ++ir) {
+      a.out[k * fa.nr + ir] = a_in.out[order[k] * fa.nr + ir];
+      a.out[k * fa.nr + ir].alpha_idx = k;
+    }
+  }
   const bool vec = (g.d % 4) == 0 && (((uintptr_t)g.X) & 15) == 0;
   return vec ? launch_vec<true>(g, a, fa, ctr, s) : launch_vec<false>(g, a, fa, ctr, s);
 }
