@@ -58,8 +58,11 @@ __device__ __forceinline__ uint32_t sq_u8_q(const uint8_t* __restrict__ qs,
   return qq + xx - 2u * dot;
 }
 
+// Queries come either as one contiguous nq x d array with contiguous outputs,
+// or (jobs != null) as one descriptor per query with its own row and outputs.
 template <int DT>
 __global__ __launch_bounds__(64) void search_kernel(GraphView g, const void* __restrict__ Q,
+                                                    const SearchJob* __restrict__ jobs,
                                                     int32_t k, int32_t L,
                                                     int32_t* __restrict__ out_ids,
                                                     double* __restrict__ out_dist,
@@ -83,6 +86,16 @@ __global__ __launch_bounds__(64) void search_kernel(GraphView g, const void* __r
   const int d = g.d;
   const size_t esz = DT == RP_U8 ? 1 : 4;
   const uint8_t* qg = (const uint8_t*)Q + (size_t)qi * d * esz;
+  int32_t* o_ids = out_ids + qi * k;
+  double* o_dist = out_dist ? out_dist + qi * k : nullptr;
+  int32_t* o_hops = out_hops ? out_hops + qi : nullptr;
+  if (jobs) {
+    const SearchJob jb = jobs[qi];
+    qg = (const uint8_t*)jb.q;
+    o_ids = jb.ids;
+    o_dist = jb.dist;
+    o_hops = jb.hops;
+  }
   for (int t = lane; t < (int)(d * esz); t += kWave) qs[t] = qg[t];
   __syncthreads();
   uint32_t qq = 0;
@@ -205,21 +218,21 @@ __global__ __launch_bounds__(64) void search_kernel(GraphView g, const void* __r
   }
 
   for (int t = lane; t < k; t += kWave) {
-    out_ids[qi * k + t] = t < cnt ? (int32_t)bL[t] : -1;
-    if (out_dist) {
+    o_ids[t] = t < cnt ? (int32_t)bL[t] : -1;
+    if (o_dist) {
       double dv = -1.0;
       if (t < cnt) dv = DT == RP_U8 ? (double)bH[t] : __longlong_as_double((long long)bH[t]);
-      out_dist[qi * k + t] = dv;
+      o_dist[t] = dv;
     }
   }
-  if (lane == 0 && out_hops) out_hops[qi] = hops;
+  if (lane == 0 && o_hops) *o_hops = hops;
 }
 
 }  // namespace
 
-hipError_t launch_search(const GraphView& g, const void* Q, int64_t nq, int32_t k, int32_t L,
-                         int32_t* out_ids, double* out_dist, int32_t* out_hops,
-                         hipStream_t s) {
+static hipError_t launch_search_any(const GraphView& g, const void* Q, const SearchJob* jobs,
+                                    int64_t nq, int32_t k, int32_t L, int32_t* out_ids,
+                                    double* out_dist, int32_t* out_hops, hipStream_t s) {
   if (nq == 0) return hipSuccess;
   const size_t cap = (size_t)L + kWave;
   const size_t esz = g.dtype == RP_U8 ? 1 : 4;
@@ -227,12 +240,23 @@ hipError_t launch_search(const GraphView& g, const void* Q, int64_t nq, int32_t 
   const size_t shmem = search_query_offset((int)cap) + (size_t)g.d * esz;
   dim3 grid((unsigned)nq), block(kWave);
   if (g.dtype == RP_U8)
-    hipLaunchKernelGGL(search_kernel<RP_U8>, grid, block, shmem, s, g, Q, k, L, out_ids,
+    hipLaunchKernelGGL(search_kernel<RP_U8>, grid, block, shmem, s, g, Q, jobs, k, L, out_ids,
                        out_dist, out_hops);
   else
-    hipLaunchKernelGGL(search_kernel<RP_F32>, grid, block, shmem, s, g, Q, k, L, out_ids,
+    hipLaunchKernelGGL(search_kernel<RP_F32>, grid, block, shmem, s, g, Q, jobs, k, L, out_ids,
                        out_dist, out_hops);
   return hipGetLastError();
+}
+
+hipError_t launch_search(const GraphView& g, const void* Q, int64_t nq, int32_t k, int32_t L,
+                         int32_t* out_ids, double* out_dist, int32_t* out_hops,
+                         hipStream_t s) {
+  return launch_search_any(g, Q, nullptr, nq, k, L, out_ids, out_dist, out_hops, s);
+}
+
+hipError_t launch_search_jobs(const GraphView& g, const SearchJob* jobs, int64_t n, int32_t k,
+                              int32_t L, hipStream_t s) {
+  return launch_search_any(g, nullptr, jobs, n, k, L, nullptr, nullptr, nullptr, s);
 }
 
 }  // namespace rp

@@ -8,19 +8,11 @@
 
 #include "rp_internal.h"
 
-struct rp_graph {
-  rp::GraphView view;
-  rp::DevCounters* ctr;
-  rp_graph* base;  // non-null for derived handles
-  int device;
-  int64_t nodes;   // vertex-prunes enqueued, counted on the host
-  void* aux;       // per-point array owned by a base handle, shared by derived ones:
-                   // |x|^2 (uint8 points) or max_k |x_k| (float32 points)
-};
+namespace rp {
 
 namespace {
-
 thread_local char g_err[512];
+}  // namespace
 
 rp_status fail(rp_status st, const char* fmt, ...) {
   va_list ap;
@@ -34,6 +26,8 @@ rp_status ok() {
   g_err[0] = 0;
   return RP_OK;
 }
+
+const char* last_error() { return g_err; }
 
 // Is [p, p + bytes) inside one device allocation?
 bool device_range(const void* p, size_t bytes) {
@@ -56,6 +50,23 @@ bool device_range(const void* p, size_t bytes) {
 }
 
 size_t elem_size(int32_t dt) { return dt == RP_U8 ? 1 : 4; }
+
+rp_status check_alpha(rp_alpha a) {
+  if (a.den < 1 || a.num < a.den || a.num > 65535)
+    return fail(RP_EINVAL, "alpha must be num/den with 1 <= den <= num <= 65535 (got %d/%d)",
+                a.num, a.den);
+  return RP_OK;
+}
+
+}  // namespace rp
+
+using rp::check_alpha;
+using rp::device_range;
+using rp::elem_size;
+using rp::fail;
+using rp::ok;
+
+namespace {
 
 rp_status check_launch(hipError_t e, const char* what) {
   if (e != hipSuccess) return fail(RP_EDEVICE, "%s: %s", what, hipGetErrorString(e));
@@ -86,13 +97,6 @@ rp_status validate_adjacency(const rp::GraphView& v, rp::DevCounters* ctr, hipSt
   return RP_OK;
 }
 
-rp_status check_alpha(rp_alpha a) {
-  if (a.den < 1 || a.num < a.den || a.num > 65535)
-    return fail(RP_EINVAL, "alpha must be num/den with 1 <= den <= num <= 65535 (got %d/%d)",
-                a.num, a.den);
-  return RP_OK;
-}
-
 rp_status check_outputs(const rp_graph* g, int32_t R, const int32_t* out_nbr,
                         const int32_t* out_deg) {
   if (R < 1) return fail(RP_EINVAL, "R must be >= 1 (got %d)", R);
@@ -111,7 +115,7 @@ rp_status check_outputs(const rp_graph* g, int32_t R, const int32_t* out_nbr,
 
 extern "C" {
 
-const char* rp_last_error(void) { return g_err; }
+const char* rp_last_error(void) { return rp::last_error(); }
 
 rp_status rp_load_graph(const void* points, int32_t dtype, int64_t n, int32_t d,
                         const int32_t* nbr, const int32_t* deg, int32_t r_max, int32_t start,

@@ -52,6 +52,15 @@ struct GraphView {
   const float* maxabs;    // max_k |x_k| per point (float32 points; library-owned), else null
 };
 
+// One query of a batched search: its row and its outputs (device pointers;
+// dist and hops nullable).
+struct SearchJob {
+  const void* q;
+  int32_t* ids;
+  double* dist;
+  int32_t* hops;
+};
+
 // Kernel launchers (each returns hipGetLastError() of its launch).
 hipError_t launch_validate(const GraphView& g, DevCounters* ctr, hipStream_t s);
 hipError_t launch_norms_u8(const GraphView& g, uint32_t* norms, hipStream_t s);
@@ -64,6 +73,8 @@ hipError_t launch_prune_batched(const GraphView& g, const SweepArgs& a, DevCount
 hipError_t launch_search(const GraphView& g, const void* Q, int64_t nq, int32_t k, int32_t L,
                          int32_t* out_ids, double* out_dist, int32_t* out_hops,
                          hipStream_t s);
+hipError_t launch_search_jobs(const GraphView& g, const SearchJob* jobs, int64_t n, int32_t k,
+                              int32_t L, hipStream_t s);
 
 // FP32 direct-difference distance bound: |S~ - S| <= gamma_{d+2} S for a
 // sequential fmaf accumulation of squared FP32 differences; doubled and
@@ -75,4 +86,24 @@ inline double f32_rel_bound(int d) {
   return 2.0 * g + 4e-12;
 }
 
+// Error state and argument checks shared by the C-ABI entry points
+// (rp_api.hip, rp_serve.hip).
+rp_status fail(rp_status st, const char* fmt, ...);
+rp_status ok();
+const char* last_error();
+bool device_range(const void* p, size_t bytes);
+size_t elem_size(int32_t dt);
+rp_status check_alpha(rp_alpha a);
+
 }  // namespace rp
+
+// A graph handle: the view the kernels read, its counters and ownership.
+struct rp_graph {
+  rp::GraphView view;
+  rp::DevCounters* ctr;
+  rp_graph* base;  // non-null for derived handles
+  int device;
+  int64_t nodes;   // vertex-prunes enqueued, counted on the host
+  void* aux;       // per-point array owned by a base handle, shared by derived ones:
+                   // |x|^2 (uint8 points) or max_k |x_k| (float32 points)
+};

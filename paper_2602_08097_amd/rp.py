@@ -36,8 +36,31 @@ class Counters(C.Structure):
     _fields_ = [("nodes", C.c_int64), ("rechecks", C.c_int64)]
 
 
+class Request(C.Structure):
+    _fields_ = [("type", C.c_int32), ("alpha", Alpha), ("R", C.c_int32),
+                ("queries", C.c_void_p), ("nq", C.c_int64), ("k", C.c_int32), ("L", C.c_int32),
+                ("out_ids", C.c_void_p), ("out_dist", C.c_void_p), ("out_hops", C.c_void_p),
+                ("tag", C.c_int64)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("tag", C.c_int64), ("status", C.c_int32), ("batch", C.c_int32),
+                ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("sweeps", C.c_int64), ("swept_alphas", C.c_int64), ("searches", C.c_int64),
+                ("searched_queries", C.c_int64), ("evictions", C.c_int64),
+                ("resident_graphs", C.c_int64), ("resident_bytes", C.c_int64)]
+
+
+REQ_PRUNE = 1
+REQ_QUERY = 2
+
 EXPORTS = ["rp_load_graph", "rp_graph_derive", "rp_prune", "rp_prune_sweep", "rp_prune_plain",
-           "rp_search", "rp_read_counters", "rp_free_graph", "rp_last_error"]
+           "rp_search", "rp_read_counters", "rp_free_graph", "rp_last_error",
+           "rp_server_create", "rp_server_submit", "rp_server_poll", "rp_server_replay",
+           "rp_server_stats_get", "rp_server_destroy"]
 
 _lib = None
 
@@ -70,6 +93,19 @@ def load_library(path: str = LIB_PATH):
     lib.rp_free_graph.argtypes = [vp]
     lib.rp_last_error.restype = C.c_char_p
     lib.rp_last_error.argtypes = []
+    lib.rp_server_create.restype = i32
+    lib.rp_server_create.argtypes = [vp, i64, i32, i32, i32, C.POINTER(vp)]
+    lib.rp_server_submit.restype = i32
+    lib.rp_server_submit.argtypes = [vp, C.POINTER(Request)]
+    lib.rp_server_poll.restype = i32
+    lib.rp_server_poll.argtypes = [vp, C.POINTER(Completion), i32, i32]
+    lib.rp_server_replay.restype = i32
+    lib.rp_server_replay.argtypes = [vp, C.POINTER(Request), C.POINTER(C.c_double), i32,
+                                     C.POINTER(Completion)]
+    lib.rp_server_stats_get.restype = i32
+    lib.rp_server_stats_get.argtypes = [vp, C.POINTER(ServerStats)]
+    lib.rp_server_destroy.restype = None
+    lib.rp_server_destroy.argtypes = [vp]
     _lib = lib
     return lib
 
@@ -207,5 +243,94 @@ class Graph:
     def __del__(self):
         try:
             self.free()
+        except Exception:
+            pass
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return t.data_ptr() if t is not None else None
+
+
+class Server:
+    """Request loop over a resident base graph (include/rp_serve.h).
+
+    Requests are built with prune_request()/query_request(); the tensors they
+    reference are kept alive by this object until the request completes
+    (completions are matched by tag)."""
+
+    def __init__(self, base: Graph, budget_bytes: int, n_streams: int = 4,
+                 max_query_batch: int = 4096, fifo: bool = False):
+        lib = load_library()
+        if base._base is not None:
+            raise ValueError("the server needs a base graph, not a derived one")
+        self.base = base
+        h = C.c_void_p()
+        _check(lib.rp_server_create(base.handle, int(budget_bytes), int(n_streams),
+                                    int(max_query_batch), 1 if fifo else 0, C.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    def prune_request(self, alpha, R: int, out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None,
+                      tag: int = 0) -> Request:
+        num, den = as_alpha(alpha)
+        nb, dg = out if out is not None else (None, None)
+        if out is not None:
+            self.base._check_out(nb, dg, R)
+        r = Request(REQ_PRUNE, Alpha(num, den), int(R), None, 0, 0, 0, _ptr(nb), None, _ptr(dg),
+                    int(tag))
+        self._keep[int(tag)] = (nb, dg)
+        return r
+
+    def query_request(self, alpha, R: int, Q: torch.Tensor, k: int, L: int,
+                      out_ids: torch.Tensor, out_dist: Optional[torch.Tensor] = None,
+                      out_hops: Optional[torch.Tensor] = None, tag: int = 0) -> Request:
+        """alpha None queries the base graph."""
+        _need_cuda(Q, out_ids, out_dist, out_hops)
+        if Q.dtype != self.base.points.dtype or Q.shape[1] != self.base.d:
+            raise ValueError("queries must match the points' dtype and dimension")
+        nq = Q.shape[0]
+        if tuple(out_ids.shape) != (nq, k) or out_ids.dtype != torch.int32:
+            raise ValueError("out_ids must be int32 (nq, k)")
+        num, den = (0, 0) if alpha is None else as_alpha(alpha)
+        r = Request(REQ_QUERY, Alpha(num, den), int(R), Q.data_ptr(), nq, int(k), int(L),
+                    out_ids.data_ptr(), _ptr(out_dist), _ptr(out_hops), int(tag))
+        self._keep[int(tag)] = (Q, out_ids, out_dist, out_hops)
+        return r
+
+    def submit(self, req: Request):
+        _check(_lib.rp_server_submit(self.handle, C.byref(req)))
+
+    def poll(self, max_n: int = 256, wait_ms: int = 0) -> List[Completion]:
+        buf = (Completion * max_n)()
+        n = _lib.rp_server_poll(self.handle, buf, max_n, int(wait_ms))
+        out = [buf[i] for i in range(max(n, 0))]
+        for c in out:
+            self._keep.pop(int(c.tag), None)
+        return out
+
+    def replay(self, reqs: Sequence[Request], arrival_s: Sequence[float]) -> List[Completion]:
+        n = len(reqs)
+        R = (Request * n)(*reqs)
+        T = (C.c_double * n)(*[float(t) for t in arrival_s])
+        out = (Completion * n)()
+        _check(_lib.rp_server_replay(self.handle, R, T, n, out))
+        for c in out:
+            self._keep.pop(int(c.tag), None)
+        return [out[i] for i in range(n)]
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(_lib.rp_server_stats_get(self.handle, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value is not None:
+            _lib.rp_server_destroy(self.handle)
+            self.handle = C.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass

@@ -6,13 +6,15 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "rp.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("rp.h", "rp_serve.h")]
 
 
 def _declared():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(rp_[a-z_]+)\s*\(", src)))
+    names = set()
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(rp_[a-z_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_header_declares_the_abi():
@@ -46,6 +48,22 @@ def test_null_arguments_are_rejected_without_a_device():
     assert b"dtype" in lib.rp_last_error()
     assert lib.rp_load_graph(None, 1, 10, 4, None, None, 4, 10, None, ctypes.byref(h)) == 2
     assert lib.rp_prune(None, rp.Alpha(6, 5), 4, None, None, None) == 5
+
+
+def test_server_arguments_are_rejected_without_a_device():
+    from paper_2602_08097_amd import rp
+
+    lib = rp.load_library()
+    h = ctypes.c_void_p()
+    assert lib.rp_server_create(None, 1 << 20, 4, 64, 0, ctypes.byref(h)) == 5
+    assert lib.rp_server_create(None, 1 << 20, 4, 64, 0, None) == 1
+    req = rp.Request(rp.REQ_PRUNE, rp.Alpha(6, 5), 8, None, 0, 0, 0, None, None, None, 0)
+    assert lib.rp_server_submit(None, ctypes.byref(req)) == 5
+    comp = (rp.Completion * 4)()
+    assert lib.rp_server_poll(None, comp, 4, 0) == -1
+    st = rp.ServerStats()
+    assert lib.rp_server_stats_get(None, ctypes.byref(st)) == 5
+    lib.rp_server_destroy(None)
 
 
 def test_oracle_library_is_separate():

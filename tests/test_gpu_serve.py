@@ -1,0 +1,166 @@
+"""Serving: a stream of prune requests at arbitrary alpha and query batches of
+varying size, replayed with Poisson arrivals through the request loop, gives
+for every request exactly what the same call gives alone (pruned graphs
+element by element; query ids, distances and visited counts), with
+continuous batching, overlap and budget evictions on, and in FIFO mode."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def setup():
+    from paper_2602_08097_amd import Graph
+
+    dev = _dev()
+    w = workloads.build("sift_u8", n=20_000, nq=2_000, device=dev)
+    X = torch.from_numpy(w.X).to(dev)
+    g0 = Graph(X, torch.from_numpy(w.knn).to(dev), torch.from_numpy(w.knn_deg).to(dev), w.start)
+    nb, dg = g0.prune((6, 5), 64)
+    torch.cuda.synchronize()
+    base = Graph(X, nb, dg, w.start)
+    Q = torch.from_numpy(w.Q).to(dev)
+    return base, Q
+
+
+def _trace(server, base, Q, n_req, seed):
+    """Requests (kept with their output tensors) and arrival times."""
+    rng = np.random.default_rng(seed)
+    dev = Q.device
+    reqs, meta = [], []
+    made = []  # (alpha, R) of prune requests so far
+    t, arrivals = 0.0, []
+    q0 = 0
+    for i in range(n_req):
+        t += rng.exponential(0.4e-3)
+        arrivals.append(t)
+        if i < 2 or rng.random() < 0.25:
+            a = (int(rng.integers(100, 121)), 100)
+            R = int(rng.choice([32, 48, 64]))
+            out = (torch.full((base.n, R), -7, dtype=torch.int32, device=dev),
+                   torch.full((base.n,), -7, dtype=torch.int32, device=dev))
+            reqs.append(server.prune_request(a, R, out=out, tag=i))
+            meta.append(("prune", a, R, out))
+            made.append((a, R))
+        else:
+            nq = int(math.floor(math.exp(rng.uniform(0, math.log(64)))))
+            if q0 + nq > Q.shape[0]:
+                q0 = 0
+            Qs = Q[q0:q0 + nq]
+            q0 += nq
+            k = int(rng.choice([10, 100]))
+            L = int(rng.choice([L for L in (100, 200) if L >= k]))
+            tgt = None if rng.random() < 0.3 else made[int(rng.integers(0, len(made)))]
+            # a graph nobody asked to prune yet: the server makes it first
+            if tgt is not None and rng.random() < 0.1:
+                tgt = ((int(rng.integers(100, 121)), 100), int(rng.choice([32, 48, 64])))
+            ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+            dist = torch.empty((nq, k), dtype=torch.float64, device=dev)
+            hops = torch.empty(nq, dtype=torch.int32, device=dev)
+            a, R = (None, 0) if tgt is None else tgt
+            reqs.append(server.query_request(a, R, Qs, k, L, ids, dist, hops, tag=i))
+            meta.append(("query", a, R, (Qs, k, L, ids, dist, hops)))
+    return reqs, meta, arrivals
+
+
+def _alone(base, meta):
+    """Every request's result computed alone through the graph API."""
+    graphs = {}
+
+    def pruned(a, R):
+        if (a, R) not in graphs:
+            nb, dg = base.prune(a, R)
+            graphs[(a, R)] = (nb, dg, base.derive(nb, dg))
+        return graphs[(a, R)]
+
+    for i, (kind, a, R, data) in enumerate(meta):
+        if kind == "prune":
+            nb, dg, _ = pruned(a, R)
+            assert torch.equal(data[0], nb), f"request {i}: pruned rows differ"
+            assert torch.equal(data[1], dg), f"request {i}: pruned degrees differ"
+        else:
+            Qs, k, L, ids, dist, hops = data
+            g = base if a is None else pruned(a, R)[2]
+            e_ids, e_dist, e_hops = g.search(Qs, k, L)
+            assert torch.equal(ids, e_ids), f"request {i}: query ids differ"
+            assert torch.equal(dist, e_dist), f"request {i}: query distances differ"
+            assert torch.equal(hops, e_hops), f"request {i}: visited counts differ"
+    for _, _, g in graphs.values():
+        g.free()
+
+
+@pytest.mark.parametrize("fifo", [False, True])
+def test_alone_equals_mix(setup, fifo):
+    from paper_2602_08097_amd import Server
+
+    base, Q = setup
+    budget = 3 * base.n * 65 * 4 + 4096  # three pruned graphs at R = 64: forces evictions
+    server = Server(base, budget, n_streams=4, max_query_batch=256, fifo=fifo)
+    reqs, meta, arrivals = _trace(server, base, Q, 120, seed=11 if fifo else 7)
+    comps = server.replay(reqs, arrivals)
+    assert all(c.status == 0 for c in comps), [c.status for c in comps if c.status]
+    assert all(c.t_done >= c.t_start >= c.t_submit for c in comps)
+    stats = server.stats()
+    server.close()
+    torch.cuda.synchronize()
+    _alone(base, meta)
+    n_queries = sum(m[3][0].shape[0] for m in meta if m[0] == "query")
+    assert stats["searched_queries"] == n_queries
+    if fifo:
+        assert max(c.batch for c in comps) == 1
+    assert stats["evictions"] > 0
+
+
+def test_batching_merges_concurrent_requests(setup):
+    """Requests that arrive together share launches: several alphas in one
+    sweep, several query requests in one search launch."""
+    from paper_2602_08097_amd import Server
+
+    base, Q = setup
+    server = Server(base, 8 * base.n * 65 * 4, n_streams=2, max_query_batch=4096)
+    dev = Q.device
+    reqs, arrivals = [], []
+    for i, a in enumerate([(101, 100), (105, 100), (110, 100), (115, 100)]):
+        reqs.append(server.prune_request(a, 64, tag=i))
+        arrivals.append(0.0)
+    outs = []
+    for i in range(4, 40):
+        ids = torch.empty((5, 10), dtype=torch.int32, device=dev)
+        outs.append(ids)
+        reqs.append(server.query_request((110, 100), 64, Q[5 * i:5 * i + 5], 10, 100, ids,
+                                         tag=i))
+        arrivals.append(0.0)
+    comps = server.replay(reqs, arrivals)
+    stats = server.stats()
+    server.close()
+    assert all(c.status == 0 for c in comps)
+    assert stats["swept_alphas"] == 4 and stats["sweeps"] < 4
+    assert stats["searches"] < 36
+    assert max(c.batch for c in comps[4:]) > 1
+
+
+def test_bad_requests_are_rejected(setup):
+    from paper_2602_08097_amd import RPError, Server
+
+    base, Q = setup
+    server = Server(base, base.n * 65 * 4 + 4096, n_streams=2, max_query_batch=64)
+    ids = torch.empty((4, 10), dtype=torch.int32, device=Q.device)
+    with pytest.raises(RPError):
+        server.submit(server.query_request(None, 0, Q[:4], 10, 5, ids))   # L < k
+    with pytest.raises(RPError):
+        server.submit(server.prune_request((9, 10), 64))                  # alpha < 1
+    with pytest.raises(RPError):
+        server.submit(server.prune_request((6, 5), 65))                   # R > r_max
+    server.close()
