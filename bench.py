@@ -247,6 +247,151 @@ def cpu_baseline(w, spec, budget_s):
                       f"{dt:.1f} s single-threaded"}
 
 
+def serve_trace(spec, n_req, rate, n_graph_ids, Qpool, dev, seed):
+    """A Poisson mix: 5% prune requests (alpha ~ U{100..120}/100, R in {32, 48, 64}),
+    95% query batches (size floor(exp U[0, ln 4096]), k in {10, 100},
+    L in {100, 200, 400}) against the base graph or one of the last six graphs
+    requested (what the budget keeps resident)."""
+    import math
+
+    import numpy as np
+    import torch
+
+    rng = np.random.default_rng(seed)
+    t, out = 0.0, []
+    made = []
+    q0 = 0
+    for i in range(n_req):
+        t += rng.exponential(1.0 / rate)
+        if i == 0 or rng.random() < 0.05:
+            a = (int(rng.integers(100, 121)), 100)
+            R = int(rng.choice(spec.Rs))
+            if (a, R) in made:
+                made.remove((a, R))
+            made = (made + [(a, R)])[-6:]
+            out.append(("prune", t, a, R, None))
+        else:
+            nq = int(math.floor(math.exp(rng.uniform(0.0, math.log(4096)))))
+            if q0 + nq > Qpool.shape[0]:
+                q0 = 0
+            k = int(rng.choice([10, 100]))
+            L = int(rng.choice([100, 200, 400]))
+            j = int(rng.integers(0, len(made) + 1))
+            a, R = (None, 0) if j == len(made) else made[j]
+            out.append(("query", t, a, R, (q0, nq, k, L)))
+            q0 += nq
+    return out
+
+
+def serve_run(server, trace, Qpool, dev):
+    import numpy as np
+    import torch
+
+    reqs, arr, kinds, nqs = [], [], [], []
+    for i, (kind, t, a, R, q) in enumerate(trace):
+        if kind == "prune":
+            reqs.append(server.prune_request(a, R, tag=i))
+            nqs.append(0)
+        else:
+            q0, nq, k, L = q
+            ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+            reqs.append(server.query_request(a, R, Qpool[q0:q0 + nq], k, L, ids, tag=i))
+            nqs.append(nq)
+        arr.append(t)
+        kinds.append(kind)
+    comps = server.replay(reqs, arr)
+    stats = server.stats()
+    lat = np.array([c.t_done - c.t_submit for c in comps])
+    bad = sum(1 for c in comps if c.status != 0)
+    t0 = min(c.t_submit for c in comps)
+    t1 = max(c.t_done for c in comps)
+    kinds = np.array(kinds)
+    nqs = np.array(nqs)
+    res = {"makespan_s": t1 - t0, "errors": bad, "stats": stats}
+    for kind in ("prune", "query"):
+        sel = kinds == kind
+        if sel.any():
+            res[kind] = {"count": int(sel.sum()),
+                         "p50_ms": float(np.percentile(lat[sel], 50) * 1e3),
+                         "p99_ms": float(np.percentile(lat[sel], 99) * 1e3),
+                         "mean_ms": float(lat[sel].mean() * 1e3)}
+    res["qps"] = float(nqs.sum() / (t1 - t0))
+    res["queries"] = int(nqs.sum())
+    return res
+
+
+def serve_main(args):
+    """Serving benchmark on the 10M x 128 uint8 workload (or --n)."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2602_08097_amd import Graph, Server
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    spec = workloads.CONFIGS["serve_u8"]
+    t0 = time.time()
+    w = workloads.build("serve_u8", n=args.n, nq=args.nq, device=dev)
+    n, d = w.X.shape
+    log(f"serve workload: n={n} d={d} ({time.time() - t0:.1f} s incl. component 128-NN)")
+    X = torch.from_numpy(w.X).to(dev)
+    g_knn = Graph(X, torch.from_numpy(w.knn).to(dev), torch.from_numpy(w.knn_deg).to(dev), w.start)
+    t0 = time.time()
+    nb, dg = g_knn.prune(spec.base_alpha, spec.base_R)
+    torch.cuda.synchronize()
+    log(f"base graph alpha={spec.base_alpha} R={spec.base_R}: {time.time() - t0:.1f} s")
+    g_knn.free()
+    start = w.start
+    del w
+    base = Graph(X, nb, dg, start)
+    Qpool = torch.from_numpy(workloads.make_queries(spec, spec.nq)).to(dev)
+    budget = 6 * n * 65 * 4 + (1 << 20)
+    # the plain kernel's time for one prune request at this size
+    pn, pd = base.prune_plain((110, 100), 64)
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    base.prune_plain((110, 100), 64, out=(pn, pd))
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - tp) * 1e3
+    tb = time.perf_counter()
+    base.prune((110, 100), 64, out=(pn, pd))
+    torch.cuda.synchronize()
+    one_ms = (time.perf_counter() - tb) * 1e3
+    del pn, pd
+    log(f"one prune request: plain kernel {plain_ms:.1f} ms, batched kernel {one_ms:.1f} ms")
+    rates = [float(r) for r in args.rates.split(",")]
+    runs = []
+    for rate in rates:
+        trace = serve_trace(spec, args.requests, rate, 0, Qpool, dev, seed=int(rate))
+        row = {"rate_req_s": rate}
+        for mode, fifo in (("batched", 0), ("fifo", 1)):
+            server = Server(base, budget, n_streams=4, max_query_batch=8192, fifo=fifo)
+            r = serve_run(server, trace, Qpool, dev)
+            server.close()
+            torch.cuda.synchronize()
+            row[mode] = r
+            log(f"rate {rate:g}/s {mode}: query p50 {r['query']['p50_ms']:.2f} ms "
+                f"p99 {r['query']['p99_ms']:.2f} ms, prune p50 {r.get('prune', {}).get('p50_ms', 0):.1f} ms "
+                f"p99 {r.get('prune', {}).get('p99_ms', 0):.1f} ms, {r['qps']:.3e} QPS, "
+                f"makespan {r['makespan_s']:.2f} s, sweeps {r['stats']['sweeps']} "
+                f"({r['stats']['swept_alphas']} alphas), searches {r['stats']['searches']}, "
+                f"evictions {r['stats']['evictions']}")
+        runs.append(row)
+    top = runs[-1]["batched"]
+    line = {"metric": "serving: query and prune request latency p50/p99 with throughput",
+            "value": top["qps"], "unit": "queries/s", "n_gpus": 1,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+            "data": "synthetic",
+            "config": {"workload": f"serve_u8: {n} x {d} uint8 mixture, base RobustPrune 6/5 "
+                                   f"R=64 over component-restricted 128-NN; Poisson mix "
+                                   f"5% prune / 95% query batches, {args.requests} requests "
+                                   f"per rate", "budget_bytes": budget,
+                       "plain_prune_ms": plain_ms, "batched_one_prune_ms": one_ms},
+            "runs": runs}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,6 +410,12 @@ def main():
     ap.add_argument("--cache", metavar="NPZ",
                     help="load the generated workload from NPZ if present, else generate and save "
                          "it there (for repeated profiler runs)")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving benchmark: Poisson mix of prune requests and query batches "
+                         "through the request loop vs the one-at-a-time FIFO baseline")
+    ap.add_argument("--rates", default="100,200,400",
+                    help="serving: request arrival rates (requests/s)")
+    ap.add_argument("--requests", type=int, default=2000, help="serving: requests per rate")
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="summarise rocprofv3 output under DIR (trace, fetch, write runs) into "
                          "DIR/summary and exit")
@@ -272,6 +423,12 @@ def main():
 
     if args.summarize_profile:
         summarize_profile(args.summarize_profile)
+        return
+    if args.serve:
+        if args.gpus != 1:
+            print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+            sys.exit(2)
+        serve_main(args)
         return
     if args.profile:
         args.no_plain = args.no_search = args.no_cpu = True

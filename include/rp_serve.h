@@ -29,9 +29,10 @@
  *   creation (each takes n (R + 1) 4 bytes, rounded up to 256).  A graph is
  *   admitted when it fits after evicting least-recently-used graphs that no
  *   launch uses; otherwise its requests wait.  The base graph is never evicted.
- * - FIFO mode (fifo != 0): the baseline the batching is compared with -- one
- *   request at a time in arrival order on one stream, prunes on the plain
- *   one-workgroup-per-vertex kernel, no merging.
+ * - FIFO modes, the baselines the batching is compared with: one request at a
+ *   time in arrival order, no merging, no overlap; fifo = 1 prunes with the
+ *   batched kernel (one alpha per launch), fifo = 2 with the plain
+ *   one-workgroup-per-vertex kernel.
  *
  * Results do not depend on scheduling: a request's outputs are identical
  * whether it runs alone or in any mix (every kernel is deterministic and
@@ -92,7 +93,7 @@ typedef struct {
  *   budget_bytes   : arena for pruned graphs (device memory, allocated here).
  *   n_streams      : 2..8 (one sweep stream, the rest for query batches).
  *   max_query_batch: queries per search launch, 1..65536.
- *   fifo           : nonzero for the one-request-at-a-time baseline.
+ *   fifo           : 0 batching; 1 or 2 the one-request-at-a-time baselines.
  * The base handle must outlive the server.
  */
 rp_status rp_server_create(rp_graph_t base, int64_t budget_bytes, int32_t n_streams,

@@ -70,7 +70,7 @@ struct Launch {
 struct rp_server {
   rp_graph* base = nullptr;
   int device = 0;
-  bool fifo = false;
+  int fifo = 0;  // 0: batching; 1: one request at a time; 2: same, prunes on the plain kernel
   int n_streams = 0;
   int32_t max_batch = 0;
   std::vector<hipStream_t> streams;
@@ -241,7 +241,7 @@ void launch_sweep(rp_server* s, std::vector<Graph*>& gs, std::vector<Req*>& reqs
   L.sweep = true;
   hipStream_t st = s->streams[0];
   bool okl = true;
-  if (s->fifo) {
+  if (s->fifo == 2) {
     Graph* g = gs[0];
     okl = rp::launch_prune_plain(s->base->view, g->num * g->num, g->den * g->den, g->R, g->nbr,
                                  g->deg, s->ctr, st) == hipSuccess;
@@ -533,11 +533,12 @@ rp_status rp_server_create(rp_graph_t base, int64_t budget_bytes, int32_t n_stre
   if (max_query_batch < 1 || max_query_batch > kMaxReqQueries)
     return rp::fail(RP_EINVAL, "max_query_batch must be in [1, %lld]", (long long)kMaxReqQueries);
   if (budget_bytes < (int64_t)kAlign) return rp::fail(RP_EINVAL, "budget_bytes too small");
+  if (fifo < 0 || fifo > 2) return rp::fail(RP_EINVAL, "fifo must be 0, 1 or 2");
   rp_server* s = new (std::nothrow) rp_server();
   if (!s) return rp::fail(RP_ENOMEM, "host allocation failed");
   s->base = base;
   s->device = base->device;
-  s->fifo = fifo != 0;
+  s->fifo = fifo;
   s->n_streams = n_streams;
   s->max_batch = max_query_batch;
   s->arena_bytes = (size_t)budget_bytes & ~(kAlign - 1);

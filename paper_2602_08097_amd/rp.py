@@ -254,19 +254,22 @@ def _ptr(t: Optional[torch.Tensor]):
 class Server:
     """Request loop over a resident base graph (include/rp_serve.h).
 
+    fifo: 0 continuous batching; 1 one request at a time (batched kernel, one
+    alpha per launch); 2 one request at a time with the plain prune kernel.
+
     Requests are built with prune_request()/query_request(); the tensors they
     reference are kept alive by this object until the request completes
     (completions are matched by tag)."""
 
     def __init__(self, base: Graph, budget_bytes: int, n_streams: int = 4,
-                 max_query_batch: int = 4096, fifo: bool = False):
+                 max_query_batch: int = 4096, fifo: int = 0):
         lib = load_library()
         if base._base is not None:
             raise ValueError("the server needs a base graph, not a derived one")
         self.base = base
         h = C.c_void_p()
         _check(lib.rp_server_create(base.handle, int(budget_bytes), int(n_streams),
-                                    int(max_query_batch), 1 if fifo else 0, C.byref(h)))
+                                    int(max_query_batch), int(fifo), C.byref(h)))
         self.handle = h
         self._keep = {}
 

@@ -101,14 +101,14 @@ def _alone(base, meta):
         g.free()
 
 
-@pytest.mark.parametrize("fifo", [False, True])
+@pytest.mark.parametrize("fifo", [0, 1, 2])
 def test_alone_equals_mix(setup, fifo):
     from paper_2602_08097_amd import Server
 
     base, Q = setup
     budget = 3 * base.n * 65 * 4 + 4096  # three pruned graphs at R = 64: forces evictions
     server = Server(base, budget, n_streams=4, max_query_batch=256, fifo=fifo)
-    reqs, meta, arrivals = _trace(server, base, Q, 120, seed=11 if fifo else 7)
+    reqs, meta, arrivals = _trace(server, base, Q, 120, seed=7 + fifo)
     comps = server.replay(reqs, arrivals)
     assert all(c.status == 0 for c in comps), [c.status for c in comps if c.status]
     assert all(c.t_done >= c.t_start >= c.t_submit for c in comps)

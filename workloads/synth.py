@@ -41,6 +41,8 @@ class Spec:
     Ls: Tuple[int, ...]
     uneven_degrees: bool    # truncate base lists to t_p ~ U{16..64}
     sample: int             # nodes the oracle checks at full size
+    knn_near: int = 0       # > 0: K-NN restricted to the point's component and this many
+                            # components with the nearest centres (labelled, not exact)
 
 
 CONFIGS = {
@@ -64,9 +66,11 @@ CONFIGS = {
     "gist_f32": Spec("gist_f32", 1_000_000, 960, "f32", 64, 0.0, 0.5, None, False, 192,
                      (6, 5), 96, ((11, 10), (1, 1)), (96, 64, 32), 1_000, 100,
                      (100, 150, 200, 300, 400), False, 20_000),
-    # Serving: 10M x 128 uint8 as sift_u8.
+    # Serving: 10M x 128 uint8 as sift_u8; base lists from the 128-NN within each
+    # point's component and the 3 components with the nearest centres.
     "serve_u8": Spec("serve_u8", 10_000_000, 128, "u8", 64, 128.0, 10.0, 20.0, False, 128,
-                     (6, 5), 64, (), (32, 48, 64), 0, 100, (100, 200, 400), False, 20_000),
+                     (6, 5), 64, (), (32, 48, 64), 20_000, 100, (100, 200, 400), False, 20_000,
+                     knn_near=3),
 }
 
 
@@ -116,12 +120,17 @@ def _mixture_params(rng, spec: Spec):
     return centres, sig
 
 
-def make_points(spec: Spec, n: Optional[int] = None, seed: int = 0) -> np.ndarray:
+def make_points_labelled(spec: Spec, n: Optional[int] = None, seed: int = 0):
+    """Points, their component labels and the component centres."""
     n = spec.n if n is None else n
     rng_pts, rng_lab, _, _, _ = _streams(seed)
     centres, sig = _mixture_params(rng_pts, spec)
     labels = rng_lab.integers(0, spec.comps, n)
-    return _mixture(rng_pts, labels, centres, sig, spec)
+    return _mixture(rng_pts, labels, centres, sig, spec), labels, centres
+
+
+def make_points(spec: Spec, n: Optional[int] = None, seed: int = 0) -> np.ndarray:
+    return make_points_labelled(spec, n, seed)[0]
 
 
 def make_queries(spec: Spec, nq: Optional[int] = None, seed: int = 0) -> np.ndarray:
@@ -246,16 +255,62 @@ def _knn_torch(X: np.ndarray, K: int, device, batch: Optional[int]) -> np.ndarra
     return out.cpu().numpy()
 
 
+def knn_by_component(X: np.ndarray, labels: np.ndarray, centres: np.ndarray, K: int, near: int,
+                     device, batch: int = 2048) -> np.ndarray:
+    """n x K int32 lists: for each uint8 point, its K nearest among the points
+    of its own component and of the `near` components with the nearest centres
+    (self excluded), ascending by S, then id within the K kept (ties at the
+    K-th place may keep either id).  A labelled stand-in for exact K-NN at a
+    size where the brute force is too costly; the lists are input data."""
+    import torch
+
+    assert X.dtype == np.uint8 and X.shape[1] * 255 * 255 * 2 < (1 << 24)
+    n, d = X.shape
+    comps = centres.shape[0]
+    cd = ((centres[:, None, :] - centres[None, :, :]) ** 2).sum(-1)
+    np.fill_diagonal(cd, np.inf)
+    nearest = np.argsort(cd, axis=1, kind="stable")[:, :near]
+    order = np.argsort(labels, kind="stable")
+    bounds = np.concatenate([[0], np.cumsum(np.bincount(labels, minlength=comps))])
+    members = [np.sort(order[bounds[c]:bounds[c + 1]]) for c in range(comps)]
+    Xt = torch.from_numpy(X).to(device)
+    Xf = Xt.to(torch.float32)                      # every partial sum is an exact integer
+    nrm = (Xt.to(torch.int64) ** 2).sum(dim=1).to(torch.float32)
+    out = torch.full((n, K), -1, dtype=torch.int32, device=device)
+    for c in range(comps):
+        mem = members[c]
+        if mem.size == 0:
+            continue
+        cand = np.sort(np.concatenate([mem] + [members[o] for o in nearest[c]]))
+        ct = torch.from_numpy(cand).to(device)
+        Xc, nc = Xf[ct], nrm[ct]
+        kk = min(K, cand.size - 1)
+        for a in range(0, mem.size, batch):
+            q = torch.from_numpy(mem[a:a + batch]).to(device)
+            S = nrm[q][:, None] + nc[None, :] - 2.0 * (Xf[q] @ Xc.T)   # exact
+            S[torch.arange(q.numel(), device=device), torch.searchsorted(ct, q)] = float("inf")
+            vals, idx = torch.topk(S, kk, dim=1, largest=False, sorted=True)
+            key = (vals.to(torch.int64) << 32) | ct[idx]
+            key, _ = torch.sort(key, dim=1)
+            out[q, :kk] = (key & 0xFFFFFFFF).to(torch.int32)
+            del S, vals, idx, key
+    torch.cuda.synchronize(device)
+    return out.cpu().numpy()
+
+
 def build(name: str, n: Optional[int] = None, nq: Optional[int] = None, seed: int = 0,
           device=None, with_knn: bool = True, knn_k: Optional[int] = None,
           sample: Optional[int] = None) -> Workload:
     """Generate one configuration (optionally scaled down to n points)."""
     spec = CONFIGS[name]
-    X = make_points(spec, n, seed)
+    X, labels, centres = make_points_labelled(spec, n, seed)
     Q = make_queries(spec, nq, seed)
     K = knn_k or spec.knn_k
-    knn = knn_lists(X, K, device) if with_knn else None
-    knn_deg = None if knn is None else np.full(X.shape[0], knn.shape[1], dtype=np.int32)
+    if with_knn and spec.knn_near > 0 and device is not None:
+        knn = knn_by_component(X, labels, centres, min(K, X.shape[0] - 1), spec.knn_near, device)
+    else:
+        knn = knn_lists(X, K, device) if with_knn else None
+    knn_deg = None if knn is None else (knn >= 0).sum(axis=1).astype(np.int32)
     targets = degree_targets(X.shape[0], seed) if spec.uneven_degrees else None
     smp = node_sample(X.shape[0], sample or spec.sample, seed)
     return Workload(spec, X, Q, knn, knn_deg, medoid(X), targets, smp)
