@@ -480,7 +480,10 @@ def main():
     outs = [g._outs(spec.Rs[o % nr]) for o in range(len(spec.sweep) * nr)]
     stream = torch.cuda.current_stream()
 
-    # ---- timed batched sweep ---------------------------------------------
+    # ---- launch tuning (vertices per workgroup), then the timed sweep -------
+    tune = g.autotune_sweep(spec.sweep, spec.Rs, outs=outs)
+    log(f"autotune: {tune['waves']} vertices per workgroup (ms for 1/2/4/8: "
+        f"{[round(x, 3) for x in tune['ms']]})")
     for _ in range(args.warmup):
         g.prune_sweep(spec.sweep, spec.Rs, outs=outs)
     torch.cuda.synchronize()
@@ -600,6 +603,7 @@ def main():
                                f"{[f'{a}/{b}' for a, b in spec.sweep]} R={list(spec.Rs)}",
                    "n": n, "d": d, "mean_base_degree": float(deg_np.mean()),
                    "rechecks_per_node_alpha": ctr["rechecks"] / max(1, ctr["nodes"]),
+                   "vertices_per_workgroup": tune["waves"],
                    "outputs_per_step": len(outs)},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -151,6 +151,43 @@ rp_status rp_search(rp_graph_t g, const void* queries, int64_t nq, int32_t k, in
  */
 rp_status rp_read_counters(rp_graph_t g, rp_counters* out, int32_t reset, void* stream);
 
+/*
+ * Captured sweeps.  rp_plan_sweep records the launches that rp_prune_sweep
+ * would enqueue for these arguments into a HIP graph (stream capture on
+ * `stream`, nothing runs) and instantiates it; rp_plan_launch replays it on
+ * any stream, with no host-side work beyond one graph launch.  The graph
+ * handle and every output array must outlive the plan.  The outputs of a
+ * replay are identical to those of the call it captured.
+ */
+typedef struct rp_plan* rp_plan_t; /* opaque, library-owned */
+
+rp_status rp_plan_sweep(rp_graph_t g, const rp_alpha* alphas, int32_t n_a, const int32_t* Rs,
+                        int32_t n_R, int32_t* const* out_nbr, int32_t* const* out_deg,
+                        void* stream, rp_plan_t* out);
+rp_status rp_plan_launch(rp_plan_t p, void* stream);
+void rp_plan_free(rp_plan_t p); /* NULL is ignored */
+
+/*
+ * Launch tuning.  The batched kernels run one vertex per wavefront and pack
+ * `waves` vertices into each workgroup (1, 2, 4 or 8, within 64 KiB of LDS
+ * per workgroup).  rp_autotune_sweep times the sweep of these arguments for
+ * every candidate (one warm-up and three timed launches each, HIP events on
+ * `stream`), keeps the fastest for this graph shape (dtype, d, r_max) and
+ * sweep shape (n_a, n_R) for the rest of the process, and returns it in
+ * *waves (host); ms (host, 4 entries, nullable) receives each candidate's
+ * median time, 0 for a candidate that does not fit.  The outputs hold the
+ * sweep's result afterwards.  Synchronises `stream`.  Graphs that take the
+ * plain kernel have nothing to tune (*waves = 1).
+ * rp_tune_set records a choice (for instance from a cache of earlier
+ * tunings); waves = 0 forgets it.  rp_tune_get returns the current choice
+ * (0 = untuned, which launches 1).
+ */
+rp_status rp_autotune_sweep(rp_graph_t g, const rp_alpha* alphas, int32_t n_a, const int32_t* Rs,
+                            int32_t n_R, int32_t* const* out_nbr, int32_t* const* out_deg,
+                            void* stream, int32_t* waves, float* ms);
+rp_status rp_tune_set(rp_graph_t g, int32_t n_a, int32_t n_R, int32_t waves);
+rp_status rp_tune_get(rp_graph_t g, int32_t n_a, int32_t n_R, int32_t* waves);
+
 /* rp_free_graph -- release a handle (NULL is ignored).  Synchronises the
  * device; the caller's arrays are not freed. */
 void rp_free_graph(rp_graph_t g);

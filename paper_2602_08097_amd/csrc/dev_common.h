@@ -166,6 +166,15 @@ __device__ __forceinline__ void wave_sort2(uint64_t& hi, uint32_t& lo, int lane)
   bitonic_step2<64, 1>(hi, lo, lane);
 }
 
+// Orders the LDS accesses of one wavefront's lanes around this point (a
+// workgroup holds several independent wavefronts, each on its own vertex and
+// its own LDS region, so no workgroup barrier is needed).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // A wave-uniform 64-bit value pinned to scalar registers.
 __device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);

@@ -3,16 +3,55 @@
 // Out-lists of at most 64 ids run the int8-MFMA kernel for uint8 points
 // (k_prune_u8.hip) or the FP16-MFMA kernel with FP64 recheck for float32
 // points (k_prune_f32.hip); other shapes run the plain kernel once per output.
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "dev_common.h"
 
 namespace rp {
+
+namespace {
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int, int, int>, int> g_tune;
+
+std::tuple<int, int, int, int, int, int> key_of(const TuneKey& k) {
+  return std::make_tuple(k.kernel, k.dtype, k.d, k.r_max, k.n_alpha, k.n_out);
+}
+}  // namespace
+
+int tuned_waves(const TuneKey& k) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(key_of(k));
+  return it == g_tune.end() ? 0 : it->second;
+}
+
+void set_tuned_waves(const TuneKey& k, int waves) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (waves < 1) g_tune.erase(key_of(k));
+  else g_tune[key_of(k)] = waves;
+}
 
 bool prune_u8_supported(const GraphView& g);
 hipError_t launch_prune_u8(const GraphView& g, const SweepArgs& a, DevCounters* ctr,
                            hipStream_t s);
 bool prune_f32_supported(const GraphView& g);
+int prune_u8_wave_lds(const GraphView& g);
+int prune_f32_wave_lds(const GraphView& g);
 hipError_t launch_prune_f32(const GraphView& g, const SweepArgs& a, DevCounters* ctr,
                             hipStream_t s);
+
+int batched_kernel(const GraphView& g) {
+  if (prune_u8_supported(g)) return kKernelU8;
+  if (prune_f32_supported(g)) return kKernelF32;
+  return 0;
+}
+
+int batched_wave_lds(const GraphView& g) {
+  if (prune_u8_supported(g)) return prune_u8_wave_lds(g);
+  if (prune_f32_supported(g)) return prune_f32_wave_lds(g);
+  return 0;
+}
 
 hipError_t launch_prune_batched(const GraphView& g, const SweepArgs& a, DevCounters* ctr,
                                 hipStream_t s) {

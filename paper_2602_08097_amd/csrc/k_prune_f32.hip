@@ -57,7 +57,7 @@ struct Shape {
   static constexpr int SP = MS + 4;                 // S~ row stride (16-byte rows, conflict-free scans)
   static constexpr int STILE_B = MS * SP * 4;       // S~ tile (overlays the chunk tile)
   static constexpr int A_B = TILE_B > STILE_B ? TILE_B : STILE_B;
-  static constexpr int LDS_B = A_B + MS * 4 + MS * 4;
+  static constexpr int LDS_B = (A_B + MS * 4 + MS * 4 + 15) & ~15;
 };
 
 struct F32Args {
@@ -163,23 +163,26 @@ __device__ __forceinline__ int ff1_u64(uint64_t v) {
 }
 
 template <int NA, int NB, bool CSUM, bool VEC>
-__global__ __launch_bounds__(64) void prune_f32_kernel(GraphView g, SweepArgs a, F32Args fa,
-                                                       DevCounters* ctr) {
+__global__ __launch_bounds__(512) void prune_f32_kernel(GraphView g, SweepArgs a, F32Args fa,
+                                                        DevCounters* ctr) {
   using SH = Shape<NB>;
   constexpr int MS = SH::MS;
   constexpr int NW = SH::NW;
   constexpr int NP = SH::NP;
   constexpr int SP = SH::SP;
-  extern __shared__ __align__(16) uint8_t lds[];
+  extern __shared__ __align__(16) uint8_t lds_all[];
+  const int wave = threadIdx.x >> 6;
+  const int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+  if (p >= g.n) return;
+  uint8_t* lds = lds_all + (size_t)wave * SH::LDS_B;  // this wavefront's vertex
   float* T = (float*)lds;                   // chunk tile, ROWS x kRowF
   float* St = (float*)lds;                  // S~ tile, MS x SP, slot order (after the Gram)
   float* sr = (float*)(lds + SH::A_B);      // S(p, slot) 2^2e in FP32
   int32_t* idl = (int32_t*)(sr + MS);       // id by slot, -1 if empty
 
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   const int l32 = lane & 31;
   const int half = lane >> 5;
-  const int64_t p = blockIdx.x;
   const int d = g.d;
   const float* X = (const float*)g.X;
 
@@ -212,7 +215,7 @@ __global__ __launch_bounds__(64) void prune_f32_kernel(GraphView g, SweepArgs a,
   const float scf = ldexpf(1.f, e);
   const double sc = ldexp(1.0, e);
   const double sc2 = sc * sc;
-  __syncthreads();
+  wave_sync();
 
   // ---- a2 + a3 + a5: streamed chunks ----------------------------------------
   const int nseg = (m + 1) * 8;   // rows 0..m-1, then x_p; 8 x 16 bytes per row
@@ -261,7 +264,7 @@ __global__ __launch_bounds__(64) void prune_f32_kernel(GraphView g, SweepArgs a,
   for (int ch = 0; ch < nch; ++ch) {
     const int c0 = ch * kDC;
     const int dc = min(kDC, d - c0);
-    __syncthreads();  // the previous chunk's reads are done
+    wave_sync();  // the previous chunk's reads are done
 #pragma unroll
     for (int t = 0; t < SH::SEG; ++t) {
       const int c = lane + 64 * t;
@@ -272,7 +275,7 @@ __global__ __launch_bounds__(64) void prune_f32_kernel(GraphView g, SweepArgs a,
       }
     }
     if (ch + 1 < nch) issue(c0 + kDC);
-    __syncthreads();
+    wave_sync();
 
     // canonical S(p, j), k ascending
     const float* xp = T + MS * kRowF;
@@ -365,7 +368,7 @@ __global__ __launch_bounds__(64) void prune_f32_kernel(GraphView g, SweepArgs a,
     const int s = lane + 64 * w;
     if (s < MS) sr[s] = (float)(sp[w] * sc2);
   }
-  __syncthreads();  // every chunk-tile read is done; sr is visible
+  wave_sync();  // every chunk-tile read is done; sr is visible
 
   // S~ tile in slot order (both triangles; one writer per entry).
   // Accumulator layout of a 32 x 32 block: lane l holds column l % 32 of rows
@@ -508,7 +511,7 @@ __global__ __launch_bounds__(64) void prune_f32_kernel(GraphView g, SweepArgs a,
       const float inv = v0 ? (s2 > 0.0 ? (float)(1.0 / s2) : 0.f) : __builtin_nanf("");
       float* invt = sr;  // S(p, .) by slot is no longer needed
       invt[lane] = inv;
-      __syncthreads();
+      wave_sync();
       float zmin = __builtin_inff();
       const float* myrow = St + lane * SP;
 #pragma unroll 4
@@ -720,6 +723,10 @@ __global__ __launch_bounds__(64) void prune_f32_kernel(GraphView g, SweepArgs a,
 
 }  // namespace
 
+int prune_f32_wave_lds(const GraphView& g) {
+  return g.r_max > 64 ? Shape<3>::LDS_B : Shape<2>::LDS_B;
+}
+
 bool prune_f32_supported(const GraphView& g) {
   return g.dtype == RP_F32 && g.r_max <= 96 && g.n <= (1ll << 25) && g.maxabs != nullptr;
 }
@@ -759,8 +766,10 @@ static void f32_bound_constants(int d, bool csum, double* c1, double* c2, double
 template <int NB, bool CSUM, bool VEC>
 static hipError_t launch_shape(const GraphView& g, const SweepArgs& a, const F32Args& fa,
                                DevCounters* ctr, hipStream_t s) {
-  const size_t shmem = Shape<NB>::LDS_B;
-  dim3 grid((unsigned)g.n), block(64);
+  const int waves =
+      waves_for(TuneKey{kKernelF32, g.dtype, g.d, g.r_max, a.n_alpha, a.n_out}, Shape<NB>::LDS_B);
+  const size_t shmem = (size_t)Shape<NB>::LDS_B * waves;
+  dim3 grid((unsigned)((g.n + waves - 1) / waves)), block(64 * waves);
 #define RP_LAUNCH_F32(NA_)                                                                  \
   case NA_:                                                                                 \
     hipLaunchKernelGGL((prune_f32_kernel<NA_, NB, CSUM, VEC>), grid, block, shmem, s, g, a, \

@@ -181,7 +181,7 @@ __device__ __forceinline__ Front node_front(const Tile& tl, const SweepArgs& a, 
     acc01 = __builtin_amdgcn_mfma_i32_32x32x32_i8(f0, f1, acc01, 0, 0, 0);
     acc11 = __builtin_amdgcn_mfma_i32_32x32x32_i8(f1, f1, acc11, 0, 0, 0);
   }
-  __syncthreads();  // every U read is done before the count tile overwrites it
+  wave_sync();  // every U read is done before the count tile overwrites it
 
   // Count tile, 3072 bytes: columns 0..31 of rows 0..31 at byte 32 i + c;
   // columns 32..63 of rows 0..63 at byte 1024 + 32 i + (c - 32).  Row i is
@@ -295,12 +295,17 @@ __device__ __forceinline__ void node_back(const Tile& tl, const SweepArgs& a, in
   }
 }
 
-// One wavefront per vertex (any d multiple of 16 up to 256).
+// One wavefront per vertex (any d multiple of 16 up to 256), blockDim.x / 64
+// vertices per workgroup, each wavefront with its own `wave_lds` bytes of LDS.
 template <int NA, int NR, bool CAP>
-__global__ __launch_bounds__(64) void prune_u8_kernel(GraphView g, SweepArgs a, int32_t idbits) {
-  extern __shared__ __align__(16) uint8_t lds[];
-  const int lane = threadIdx.x;
-  const int64_t p = blockIdx.x;
+__global__ __launch_bounds__(512) void prune_u8_kernel(GraphView g, SweepArgs a, int32_t idbits,
+                                                       int32_t wave_lds) {
+  extern __shared__ __align__(16) uint8_t lds_all[];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+  if (p >= g.n) return;
+  uint8_t* lds = lds_all + (size_t)wave * wave_lds;
   const int d = g.d;
   const Tile tl = make_tile(lds, d);
   int32_t* idl = tl.nr + 64;  // listed ids by slot, then p
@@ -309,7 +314,7 @@ __global__ __launch_bounds__(64) void prune_u8_kernel(GraphView g, SweepArgs a, 
   const int id = load_list(g, p, lane);
   idl[lane] = id;
   if (lane == 0) idl[64] = (int)p;
-  __syncthreads();
+  wave_sync();
 
   // ---- a2: coalesced gather into LDS (u = x - 128) -----------------------
   // Every load of a batch is issued before any of its stores.
@@ -343,39 +348,50 @@ __global__ __launch_bounds__(64) void prune_u8_kernel(GraphView g, SweepArgs a, 
       }
     }
   }
-  __syncthreads();
+  wave_sync();
   const Front f = node_front<NA>(tl, a, d, p, id, lane, idbits);
-  __syncthreads();
+  wave_sync();
   node_back<NA, NR, CAP>(tl, a, p, f, lane);
 }
 
+struct Launch {
+  int idbits;
+  int wave_lds;  // LDS bytes per wavefront
+  int waves;     // vertices per workgroup
+};
+
 template <int NA, int NR>
-hipError_t launch_nr(const GraphView& g, const SweepArgs& a, int idbits, size_t shmem,
-                     hipStream_t s) {
+hipError_t launch_nr(const GraphView& g, const SweepArgs& a, const Launch& L, hipStream_t s) {
   bool cap = false;
   for (int o = 0; o < a.n_out; ++o) cap = cap || a.out[o].R < g.r_max;
+  const dim3 grid((unsigned)((g.n + L.waves - 1) / L.waves)), block(64 * L.waves);
+  const size_t shmem = (size_t)L.wave_lds * L.waves;
   if (cap)
-    hipLaunchKernelGGL((prune_u8_kernel<NA, NR, true>), dim3((unsigned)g.n), dim3(64), shmem, s,
-                       g, a, idbits);
+    hipLaunchKernelGGL((prune_u8_kernel<NA, NR, true>), grid, block, shmem, s, g, a, L.idbits,
+                       L.wave_lds);
   else
-    hipLaunchKernelGGL((prune_u8_kernel<NA, NR, false>), dim3((unsigned)g.n), dim3(64), shmem,
-                       s, g, a, idbits);
+    hipLaunchKernelGGL((prune_u8_kernel<NA, NR, false>), grid, block, shmem, s, g, a, L.idbits,
+                       L.wave_lds);
   return hipGetLastError();
 }
 
 template <int NA>
-hipError_t launch_na(const GraphView& g, const SweepArgs& a, int idbits, size_t shmem,
-                     hipStream_t s) {
+hipError_t launch_na(const GraphView& g, const SweepArgs& a, const Launch& L, hipStream_t s) {
   switch (a.n_out / NA) {
-    case 1: return launch_nr<NA, 1>(g, a, idbits, shmem, s);
-    case 2: return launch_nr<NA, 2>(g, a, idbits, shmem, s);
-    case 3: return launch_nr<NA, 3>(g, a, idbits, shmem, s);
-    case 4: return launch_nr<NA, 4>(g, a, idbits, shmem, s);
+    case 1: return launch_nr<NA, 1>(g, a, L, s);
+    case 2: return launch_nr<NA, 2>(g, a, L, s);
+    case 3: return launch_nr<NA, 3>(g, a, L, s);
+    case 4: return launch_nr<NA, 4>(g, a, L, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 }  // namespace
+
+int prune_u8_wave_lds(const GraphView& g) {
+  const int stride = u_stride(g.d);
+  return (max(65 * stride, kSTileBytes) + (64 + 68) * (int)sizeof(int32_t) + 15) & ~15;
+}
 
 bool prune_u8_supported(const GraphView& g) {
   return g.dtype == RP_U8 && g.r_max <= 64 && (g.d % 16) == 0 && g.d <= kMaxDimU8 &&
@@ -412,17 +428,19 @@ hipError_t launch_prune_u8(const GraphView& g, const SweepArgs& a_in, DevCounter
   }
   int idbits = 1;
   while ((1ll << idbits) < g.n) ++idbits;
-  const int stride = u_stride(g.d);
-  const size_t shmem = (size_t)max(65 * stride, kSTileBytes) + (64 + 68) * sizeof(int32_t);
+  Launch L;
+  L.idbits = idbits;
+  L.wave_lds = prune_u8_wave_lds(g);
+  L.waves = waves_for(TuneKey{kKernelU8, g.dtype, g.d, g.r_max, a.n_alpha, a.n_out}, L.wave_lds);
   switch (a.n_alpha) {
-    case 1: return launch_na<1>(g, a, idbits, shmem, s);
-    case 2: return launch_na<2>(g, a, idbits, shmem, s);
-    case 3: return launch_na<3>(g, a, idbits, shmem, s);
-    case 4: return launch_na<4>(g, a, idbits, shmem, s);
-    case 5: return launch_na<5>(g, a, idbits, shmem, s);
-    case 6: return launch_na<6>(g, a, idbits, shmem, s);
-    case 7: return launch_na<7>(g, a, idbits, shmem, s);
-    case 8: return launch_na<8>(g, a, idbits, shmem, s);
+    case 1: return launch_na<1>(g, a, L, s);
+    case 2: return launch_na<2>(g, a, L, s);
+    case 3: return launch_na<3>(g, a, L, s);
+    case 4: return launch_na<4>(g, a, L, s);
+    case 5: return launch_na<5>(g, a, L, s);
+    case 6: return launch_na<6>(g, a, L, s);
+    case 7: return launch_na<7>(g, a, L, s);
+    case 8: return launch_na<8>(g, a, L, s);
     default: return hipErrorInvalidValue;
   }
 }

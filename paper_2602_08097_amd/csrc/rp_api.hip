@@ -2,6 +2,7 @@
 // dispatch to the kernels.  Every device array is checked on the host to lie
 // inside a device allocation large enough for the sizes given, so that a
 // wrong size or a host pointer becomes RP_EINVAL instead of a GPU fault.
+#include <algorithm>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -217,9 +218,18 @@ rp_status rp_prune_plain(rp_graph_t g, rp_alpha alpha, int32_t R, int32_t* out_n
   return ok();
 }
 
-rp_status rp_prune_sweep(rp_graph_t g, const rp_alpha* alphas, int32_t n_a, const int32_t* Rs,
-                         int32_t n_R, int32_t* const* out_nbr, int32_t* const* out_deg,
-                         void* stream) {
+struct rp_plan {
+  rp_graph* g;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  int64_t nodes;  // vertex-prunes per launch
+};
+
+namespace {
+
+rp_status sweep_args(rp_graph_t g, const rp_alpha* alphas, int32_t n_a, const int32_t* Rs,
+                     int32_t n_R, int32_t* const* out_nbr, int32_t* const* out_deg,
+                     rp::SweepArgs* a_out) {
   if (!g) return fail(RP_ESTATE, "graph is null");
   if (!alphas || !Rs || !out_nbr || !out_deg) return fail(RP_EINVAL, "null host array");
   if (n_a < 1 || n_a > rp::kMaxAlphas)
@@ -242,6 +252,151 @@ rp_status rp_prune_sweep(rp_graph_t g, const rp_alpha* alphas, int32_t n_a, cons
       if (st != RP_OK) return st;
       a.out[o] = {out_nbr[o], out_deg[o], Rs[ir], ia};
     }
+  *a_out = a;
+  return RP_OK;
+}
+
+}  // namespace
+
+rp_status rp_plan_sweep(rp_graph_t g, const rp_alpha* alphas, int32_t n_a, const int32_t* Rs,
+                        int32_t n_R, int32_t* const* out_nbr, int32_t* const* out_deg,
+                        void* stream, rp_plan_t* out) {
+  if (!out) return fail(RP_EINVAL, "out is null");
+  *out = nullptr;
+  rp::SweepArgs a;
+  rp_status st = sweep_args(g, alphas, n_a, Rs, n_R, out_nbr, out_deg, &a);
+  if (st != RP_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (!s) return fail(RP_EINVAL, "capture needs a non-default stream");
+  rp_plan* p = new (std::nothrow) rp_plan();
+  if (!p) return fail(RP_ENOMEM, "host allocation failed");
+  p->g = g;
+  p->nodes = g->view.n * a.n_out;
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    const hipError_t le = rp::launch_prune_batched(g->view, a, g->ctr, s);
+    e = hipStreamEndCapture(s, &p->graph);
+    if (le != hipSuccess) e = le;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    delete p;
+    return fail(RP_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+  }
+  *out = p;
+  return ok();
+}
+
+rp_status rp_plan_launch(rp_plan_t p, void* stream) {
+  if (!p) return fail(RP_ESTATE, "plan is null");
+  rp_status st = check_launch(hipGraphLaunch(p->exec, (hipStream_t)stream), "graph launch");
+  if (st != RP_OK) return st;
+  p->g->nodes += p->nodes;
+  return ok();
+}
+
+void rp_plan_free(rp_plan_t p) {
+  if (!p) return;
+  (void)hipGraphExecDestroy(p->exec);
+  (void)hipGraphDestroy(p->graph);
+  delete p;
+}
+
+rp_status rp_tune_set(rp_graph_t g, int32_t n_a, int32_t n_R, int32_t waves) {
+  if (!g) return fail(RP_ESTATE, "graph is null");
+  if (n_a < 1 || n_a > rp::kMaxAlphas || n_R < 1 || n_R > rp::kMaxRs)
+    return fail(RP_EINVAL, "bad sweep shape");
+  if (waves != 0 && waves != 1 && waves != 2 && waves != 4 && waves != 8)
+    return fail(RP_EINVAL, "waves must be 0, 1, 2, 4 or 8");
+  const rp::GraphView& v = g->view;
+  rp::set_tuned_waves(rp::TuneKey{rp::batched_kernel(v), v.dtype, v.d, v.r_max, n_a, n_a * n_R},
+                      waves);
+  return ok();
+}
+
+rp_status rp_tune_get(rp_graph_t g, int32_t n_a, int32_t n_R, int32_t* waves) {
+  if (!g) return fail(RP_ESTATE, "graph is null");
+  if (!waves) return fail(RP_EINVAL, "waves is null");
+  const rp::GraphView& v = g->view;
+  *waves = rp::tuned_waves(
+      rp::TuneKey{rp::batched_kernel(v), v.dtype, v.d, v.r_max, n_a, n_a * n_R});
+  return ok();
+}
+
+rp_status rp_autotune_sweep(rp_graph_t g, const rp_alpha* alphas, int32_t n_a, const int32_t* Rs,
+                            int32_t n_R, int32_t* const* out_nbr, int32_t* const* out_deg,
+                            void* stream, int32_t* waves, float* ms) {
+  if (!waves) return fail(RP_EINVAL, "waves is null");
+  rp::SweepArgs a;
+  rp_status st = sweep_args(g, alphas, n_a, Rs, n_R, out_nbr, out_deg, &a);
+  if (st != RP_OK) return st;
+  const rp::GraphView& v = g->view;
+  const rp::TuneKey key{rp::batched_kernel(v), v.dtype, v.d, v.r_max, n_a, a.n_out};
+  hipStream_t s = (hipStream_t)stream;
+  static const int kCand[4] = {1, 2, 4, 8};
+  if (ms)
+    for (int i = 0; i < 4; ++i) ms[i] = 0.f;
+  if (key.kernel == 0) {
+    *waves = 1;
+    return check_launch(rp::launch_prune_batched(v, a, g->ctr, s), "prune_batched") == RP_OK
+               ? ok()
+               : RP_EDEVICE;
+  }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return check_launch(hipGetLastError(), "event create");
+  int best = 1;
+  float best_ms = 0.f;
+  int64_t launches = 0;
+  const int before = rp::tuned_waves(key);
+  hipError_t err = hipSuccess;
+  for (int c = 0; c < 4 && err == hipSuccess; ++c) {
+    const int w = kCand[c];
+    if ((size_t)w * rp::batched_wave_lds(v) > (size_t)rp::kMaxLdsPerGroup) continue;
+    rp::set_tuned_waves(key, w);
+    float t[3];
+    err = rp::launch_prune_batched(v, a, g->ctr, s);  // warm-up
+    ++launches;
+    for (int r = 0; r < 3 && err == hipSuccess; ++r) {
+      err = hipEventRecord(e0, s);
+      ++launches;
+      if (err == hipSuccess) err = rp::launch_prune_batched(v, a, g->ctr, s);
+      if (err == hipSuccess) err = hipEventRecord(e1, s);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      if (err == hipSuccess) err = hipEventElapsedTime(&t[r], e0, e1);
+    }
+    if (err != hipSuccess) break;
+    std::sort(t, t + 3);
+    if (ms) ms[c] = t[1];
+    if (c == 0 || t[1] < best_ms) {
+      best = w;
+      best_ms = t[1];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) {
+    rp::set_tuned_waves(key, before);
+    return check_launch(err, "autotune");
+  }
+  rp::set_tuned_waves(key, best);
+  // the outputs end with the chosen configuration's result
+  st = check_launch(rp::launch_prune_batched(v, a, g->ctr, s), "prune_batched");
+  if (st == RP_OK) st = check_launch(hipStreamSynchronize(s), "autotune sync");
+  if (st != RP_OK) return st;
+  g->nodes += v.n * a.n_out * (launches + 1);
+  *waves = best;
+  return ok();
+}
+
+rp_status rp_prune_sweep(rp_graph_t g, const rp_alpha* alphas, int32_t n_a, const int32_t* Rs,
+                         int32_t n_R, int32_t* const* out_nbr, int32_t* const* out_deg,
+                         void* stream) {
+  rp::SweepArgs a;
+  rp_status st0 = sweep_args(g, alphas, n_a, Rs, n_R, out_nbr, out_deg, &a);
+  if (st0 != RP_OK) return st0;
   rp_status st = check_launch(rp::launch_prune_batched(g->view, a, g->ctr, (hipStream_t)stream),
                               "prune_batched");
   if (st != RP_OK) return st;

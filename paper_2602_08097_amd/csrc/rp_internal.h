@@ -86,6 +86,27 @@ inline double f32_rel_bound(int d) {
   return 2.0 * g + 4e-12;
 }
 
+// Launch tuning: vertices per workgroup (one wavefront each) of the batched
+// prune kernels, per graph shape and sweep shape.  Untuned shapes use 1.
+constexpr int kKernelU8 = 1;
+constexpr int kKernelF32 = 2;
+constexpr int kMaxLdsPerGroup = 65536;
+struct TuneKey {
+  int32_t kernel, dtype, d, r_max, n_alpha, n_out;
+};
+int tuned_waves(const TuneKey& k);           // 0 if the shape is not tuned
+void set_tuned_waves(const TuneKey& k, int waves);
+int batched_kernel(const GraphView& g);      // kKernelU8, kKernelF32 or 0 (plain)
+int batched_wave_lds(const GraphView& g);    // LDS bytes per wavefront of that kernel
+// waves per workgroup to launch with: the tuned value, else 1; never more than
+// the LDS per workgroup allows
+inline int waves_for(const TuneKey& k, int wave_lds) {
+  int w = tuned_waves(k);
+  if (w < 1) w = 1;
+  while (w > 1 && (size_t)w * wave_lds > (size_t)kMaxLdsPerGroup) w >>= 1;
+  return w;
+}
+
 // Error state and argument checks shared by the C-ABI entry points
 // (rp_api.hip, rp_serve.hip).
 rp_status fail(rp_status st, const char* fmt, ...);

@@ -59,6 +59,8 @@ REQ_QUERY = 2
 
 EXPORTS = ["rp_load_graph", "rp_graph_derive", "rp_prune", "rp_prune_sweep", "rp_prune_plain",
            "rp_search", "rp_read_counters", "rp_free_graph", "rp_last_error",
+           "rp_plan_sweep", "rp_plan_launch", "rp_plan_free",
+           "rp_autotune_sweep", "rp_tune_set", "rp_tune_get",
            "rp_server_create", "rp_server_submit", "rp_server_poll", "rp_server_replay",
            "rp_server_stats_get", "rp_server_destroy"]
 
@@ -93,6 +95,21 @@ def load_library(path: str = LIB_PATH):
     lib.rp_free_graph.argtypes = [vp]
     lib.rp_last_error.restype = C.c_char_p
     lib.rp_last_error.argtypes = []
+    lib.rp_plan_sweep.restype = i32
+    lib.rp_plan_sweep.argtypes = [vp, C.POINTER(Alpha), i32, C.POINTER(i32), i32,
+                                  C.POINTER(vp), C.POINTER(vp), vp, C.POINTER(vp)]
+    lib.rp_plan_launch.restype = i32
+    lib.rp_plan_launch.argtypes = [vp, vp]
+    lib.rp_plan_free.restype = None
+    lib.rp_plan_free.argtypes = [vp]
+    lib.rp_autotune_sweep.restype = i32
+    lib.rp_autotune_sweep.argtypes = [vp, C.POINTER(Alpha), i32, C.POINTER(i32), i32,
+                                      C.POINTER(vp), C.POINTER(vp), vp, C.POINTER(i32),
+                                      C.POINTER(C.c_float)]
+    lib.rp_tune_set.restype = i32
+    lib.rp_tune_set.argtypes = [vp, i32, i32, i32]
+    lib.rp_tune_get.restype = i32
+    lib.rp_tune_get.argtypes = [vp, i32, i32, C.POINTER(i32)]
     lib.rp_server_create.restype = i32
     lib.rp_server_create.argtypes = [vp, i64, i32, i32, i32, C.POINTER(vp)]
     lib.rp_server_submit.restype = i32
@@ -215,6 +232,64 @@ class Graph:
         _check(_lib.rp_prune_sweep(self.handle, A, na, RR, nr, NB, DG, _stream_ptr(stream)))
         return outs
 
+    def plan_sweep(self, alphas: Sequence, Rs: Sequence[int], outs=None, stream=None) -> "Plan":
+        """Capture prune_sweep(alphas, Rs, outs) into a HIP graph (nothing runs);
+        Plan.launch() replays it.  `stream` must not be the default stream."""
+        al = [as_alpha(a) for a in alphas]
+        na, nr = len(al), len(Rs)
+        if outs is None:
+            outs = [self._outs(Rs[o % nr]) for o in range(na * nr)]
+        for o, (nb, dg) in enumerate(outs):
+            self._check_out(nb, dg, int(Rs[o % nr]))
+        A = (Alpha * na)(*[Alpha(a, b) for a, b in al])
+        RR = (C.c_int32 * nr)(*[int(r) for r in Rs])
+        NB = (C.c_void_p * (na * nr))(*[o[0].data_ptr() for o in outs])
+        DG = (C.c_void_p * (na * nr))(*[o[1].data_ptr() for o in outs])
+        h = C.c_void_p()
+        _check(_lib.rp_plan_sweep(self.handle, A, na, RR, nr, NB, DG, _stream_ptr(stream),
+                                  C.byref(h)))
+        return Plan(h, self, outs)
+
+    def _tune_key(self, na: int, nr: int) -> str:
+        return f"{'u8' if self.points.dtype == torch.uint8 else 'f32'}:d{self.d}:r{self.r_max}:a{na}:R{nr}"
+
+    def autotune_sweep(self, alphas: Sequence, Rs: Sequence[int], outs=None, cache: str = None,
+                       stream=None) -> dict:
+        """Choose the vertices per workgroup of the batched kernel for this
+        graph shape and sweep shape (timed on this graph, or read from the
+        JSON file `cache`, which then records the choice).  Returns
+        {"waves": w, "ms": [per candidate 1, 2, 4, 8] or None, "cached": bool}."""
+        import json
+
+        al = [as_alpha(a) for a in alphas]
+        na, nr = len(al), len(Rs)
+        key = self._tune_key(na, nr)
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+        if key in table:
+            _check(_lib.rp_tune_set(self.handle, na, nr, int(table[key]["waves"])))
+            return {"waves": int(table[key]["waves"]), "ms": table[key].get("ms"), "cached": True}
+        if outs is None:
+            outs = [self._outs(Rs[o % nr]) for o in range(na * nr)]
+        for o, (nb, dg) in enumerate(outs):
+            self._check_out(nb, dg, int(Rs[o % nr]))
+        A = (Alpha * na)(*[Alpha(a, b) for a, b in al])
+        RR = (C.c_int32 * nr)(*[int(r) for r in Rs])
+        NB = (C.c_void_p * (na * nr))(*[o[0].data_ptr() for o in outs])
+        DG = (C.c_void_p * (na * nr))(*[o[1].data_ptr() for o in outs])
+        w = C.c_int32()
+        ms = (C.c_float * 4)()
+        _check(_lib.rp_autotune_sweep(self.handle, A, na, RR, nr, NB, DG, _stream_ptr(stream),
+                                      C.byref(w), ms))
+        res = {"waves": int(w.value), "ms": [float(x) for x in ms], "cached": False}
+        if cache:
+            table[key] = {"waves": res["waves"], "ms": res["ms"]}
+            with open(cache, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+        return res
+
     def search(self, Q: torch.Tensor, k: int, L: int, want_dist: bool = True, stream=None):
         _need_cuda(Q)
         if Q.dtype != self.points.dtype or Q.shape[1] != self.d:
@@ -238,6 +313,28 @@ class Graph:
     def free(self):
         if getattr(self, "handle", None) is not None and self.handle.value is not None:
             _lib.rp_free_graph(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Plan:
+    """A captured sweep (keeps its graph and outputs alive)."""
+
+    def __init__(self, handle, graph: Graph, outs):
+        self.handle, self.graph, self.outs = handle, graph, outs
+
+    def launch(self, stream=None):
+        _check(_lib.rp_plan_launch(self.handle, _stream_ptr(stream)))
+        return self.outs
+
+    def free(self):
+        if getattr(self, "handle", None) is not None and self.handle.value is not None:
+            _lib.rp_plan_free(self.handle)
             self.handle = C.c_void_p()
 
     def __del__(self):

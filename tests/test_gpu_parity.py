@@ -376,3 +376,68 @@ def test_counters_and_determinism(sift_small):
     assert c["rechecks"] == 0  # integer data never needs a recheck
     a2 = [tuple(_np(t).tobytes() for t in o) for o in g.prune_sweep(spec.sweep, spec.Rs)]
     assert a1 == a2
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_captured_sweep_replays_match_eager(dtype):
+    """A sweep captured in a HIP graph and replayed several times, with eager
+    work and synchronisations between the replays, rewrites outputs identical
+    to the eager sweep every time."""
+    dev = _dev()
+    name = "sift_u8" if dtype == "u8" else "deep_f32"
+    w = workloads.build(name, n=5000, nq=10, device=dev)
+    spec = w.spec
+    g0 = _graph(w.X, w.knn, w.knn_deg, w.start)
+    nb, dg = g0.prune(spec.base_alpha, spec.base_R)
+    g = g0.derive(nb, dg)
+    alphas, Rs = list(spec.sweep[:4]), [spec.base_R, 16]
+    eager = g.prune_sweep(alphas, Rs)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan = g.plan_sweep(alphas, Rs, stream=s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for o in plan.outs:
+            o[0].fill_(-7)
+            o[1].fill_(-7)
+        torch.cuda.synchronize()
+        outs = plan.launch(stream=s)
+        s.synchronize()
+        for (a_nb, a_dg), (b_nb, b_dg) in zip(outs, eager):
+            assert torch.equal(a_nb, b_nb) and torch.equal(a_dg, b_dg), f"replay {rep}"
+        _ = (torch.ones(1000, device=dev) * rep).sum().item()  # eager work between replays
+    plan.free()
+
+
+@pytest.mark.parametrize("name,n", [("sift_u8", 20_000), ("deep_f32", 6_000), ("gist_f32", 1_500)])
+def test_vertices_per_workgroup_and_autotune(name, n, tmp_path):
+    """Packing 1, 2, 4 or 8 vertices into a workgroup (one wavefront each)
+    changes nothing in the outputs; the autotuner picks one of them, records
+    it in its cache and reads it back."""
+    from paper_2602_08097_amd import rp
+
+    dev = _dev()
+    w = workloads.build(name, n=n, nq=10, device=dev)
+    spec = w.spec
+    g0 = _graph(w.X, w.knn, w.knn_deg, w.start)
+    nb, dg = g0.prune(spec.base_alpha, spec.base_R)
+    g = g0.derive(nb, dg)
+    alphas, Rs = list(spec.sweep[:4]), list(spec.Rs)
+    na, nr = len(alphas), len(Rs)
+    rp._check(rp._lib.rp_tune_set(g.handle, na, nr, 1))
+    ref = g.prune_sweep(alphas, Rs)
+    for waves in (2, 4, 8):
+        rp._check(rp._lib.rp_tune_set(g.handle, na, nr, waves))
+        got = g.prune_sweep(alphas, Rs)
+        for (a_nb, a_dg), (b_nb, b_dg) in zip(got, ref):
+            assert torch.equal(a_nb, b_nb) and torch.equal(a_dg, b_dg), f"waves={waves}"
+    cache = str(tmp_path / "tune.json")
+    res = g.autotune_sweep(alphas, Rs, cache=cache)
+    assert res["waves"] in (1, 2, 4, 8) and not res["cached"]
+    assert res["ms"][0] > 0
+    again = g.autotune_sweep(alphas, Rs, cache=cache)
+    assert again["cached"] and again["waves"] == res["waves"]
+    got = g.prune_sweep(alphas, Rs)
+    for (a_nb, a_dg), (b_nb, b_dg) in zip(got, ref):
+        assert torch.equal(a_nb, b_nb) and torch.equal(a_dg, b_dg)
+    rp._check(rp._lib.rp_tune_set(g.handle, na, nr, 0))
