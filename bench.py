@@ -507,6 +507,15 @@ def main():
         f"{value:.3e} nodes/s; mean out-degree per alpha "
         f"{[round(float(x.mean()), 2) for x in out_degs]}")
 
+    gram_err = None
+    if w.X.dtype == np.float32 and spec.base_R <= 96:
+        smp = torch.from_numpy(w.sample[:2000].astype(np.int32)).to(dev)
+        gram_err = g.gram_error(smp)
+        log(f"distance error of the FP16 Gram vs canonical FP64 on 2000 vertices: "
+            f"max rel {gram_err['max_rel']:.3e}, mean rel {gram_err['mean_rel']:.3e}, "
+            f"max error / proven band {gram_err['max_err_over_bound']:.3f} "
+            f"({gram_err['pairs']} pairs)")
+
     esz = 1 if w.X.dtype == np.uint8 else 4
     Rs_out = [spec.Rs[o % nr] for o in range(len(spec.sweep) * nr)]
     abytes = algorithmic_bytes(deg_np, d, esz, Rs_out)
@@ -606,6 +615,9 @@ def main():
                    "vertices_per_workgroup": tune["waves"],
                    "outputs_per_step": len(outs)},
         "roofline": roofline,
+        "distance_error": gram_err if gram_err is not None else
+        ({"max_rel": 0.0, "mean_rel": 0.0, "note": "uint8: exact int32 distances"}
+         if w.X.dtype == np.uint8 else None),
         "cpu_baseline": cpu,
         "plain": plain,
         "search": search,

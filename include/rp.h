@@ -188,6 +188,21 @@ rp_status rp_autotune_sweep(rp_graph_t g, const rp_alpha* alphas, int32_t n_a, c
 rp_status rp_tune_set(rp_graph_t g, int32_t n_a, int32_t n_R, int32_t waves);
 rp_status rp_tune_get(rp_graph_t g, int32_t n_a, int32_t n_R, int32_t* waves);
 
+/*
+ * rp_gram_error -- measured error of the float32 batched kernel's approximate
+ * candidate distances.  For each listed vertex p (nodes: device int32, each in
+ * [0, n)), the kernel's own S~(i, j) for every pair of listed candidates is
+ * compared with the canonical FP64 S(i, j):
+ *   out[0] = max |S~ - S| / S,  out[1] = mean of the same,  out[2] = pairs,
+ *   out[3] = max |S~ - S| / E_j, where E_j is the bound the kernel proves and
+ *            uses to decide which pairs to recompute in FP64 (<= 1 means
+ *            every approximate decision was safe).
+ * out is a host array of 4 doubles.  Float32 graphs with out-lists of at most
+ * 96 ids only (uint8 distances are exact integers).  Synchronises `stream`.
+ */
+rp_status rp_gram_error(rp_graph_t g, const int32_t* nodes, int64_t n_nodes, double* out,
+                        void* stream);
+
 /* rp_free_graph -- release a handle (NULL is ignored).  Synchronises the
  * device; the caller's arrays are not freed. */
 void rp_free_graph(rp_graph_t g);

@@ -63,6 +63,10 @@ struct Shape {
 struct F32Args {
   double c1, c2, c3;  // rounding band of S~ (scaled units)
   int32_t nr;         // outputs per alpha (outputs are alpha-major)
+  // measurement mode: only the listed vertices, S~ compared with canonical FP64
+  const int32_t* nodes;
+  int64_t n_nodes;
+  GramErrorStats* stats;
 };
 
 // Next float toward -inf / +inf (finite inputs).
@@ -162,7 +166,10 @@ __device__ __forceinline__ int ff1_u64(uint64_t v) {
   return i;  // -1 for an empty mask
 }
 
-template <int NA, int NB, bool CSUM, bool VEC>
+// DIAG: measure instead of prune -- for the listed vertices, every candidate
+// pair's S~ is compared with the canonical FP64 S(i, j) (relative error, and
+// error over the proven band E_j), and nothing is written.
+template <int NA, int NB, bool CSUM, bool VEC, bool DIAG = false>
 __global__ __launch_bounds__(512) void prune_f32_kernel(GraphView g, SweepArgs a, F32Args fa,
                                                         DevCounters* ctr) {
   using SH = Shape<NB>;
@@ -172,7 +179,11 @@ __global__ __launch_bounds__(512) void prune_f32_kernel(GraphView g, SweepArgs a
   constexpr int SP = SH::SP;
   extern __shared__ __align__(16) uint8_t lds_all[];
   const int wave = threadIdx.x >> 6;
-  const int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+  int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+  if (DIAG) {
+    if (p >= fa.n_nodes) return;
+    p = fa.nodes[p];
+  }
   if (p >= g.n) return;
   uint8_t* lds = lds_all + (size_t)wave * SH::LDS_B;  // this wavefront's vertex
   float* T = (float*)lds;                   // chunk tile, ROWS x kRowF
@@ -397,6 +408,49 @@ __global__ __launch_bounds__(512) void prune_f32_kernel(GraphView g, SweepArgs a
         }
       }
     }
+  }
+
+  if constexpr (DIAG) {
+    wave_sync();
+    double max_rel = 0.0, sum_rel = 0.0, max_band = 0.0;
+    unsigned long long pairs = 0;
+    for (int i = 0; i < m && i < MS; ++i) {
+      const int idi = idl[i];
+      if (idi < 0) continue;  // uniform
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const int j = lane + 64 * w;
+        if (j > i && j < m && j < MS && idw[w] >= 0 && idw[w] != idi) {
+          const double ex = canon_rows<VEC>(X + (int64_t)idi * d, X + (int64_t)idw[w] * d, d);
+          const double ap = (double)St[i * SP + j];
+          const double err = fabs(ap - ex * sc2);
+          if (ex > 0.0) {
+            const double rel = err / (ex * sc2);
+            max_rel = fmax(max_rel, rel);
+            sum_rel += rel;
+          }
+          const double s2 = fmax((double)sr[i], (double)sr[j]) * (1.0 + 0x1p-20);
+          const double E = fa.c1 * s2 + fa.c2 * sqrt(s2) + fa.c3;
+          max_band = fmax(max_band, err / E);
+          ++pairs;
+        }
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      max_rel = fmax(max_rel, __shfl_xor(max_rel, off, 64));
+      max_band = fmax(max_band, __shfl_xor(max_band, off, 64));
+      sum_rel += __shfl_xor(sum_rel, off, 64);
+      pairs += __shfl_xor(pairs, off, 64);
+    }
+    if (lane == 0) {
+      atomicMax((unsigned long long*)&fa.stats->max_rel,
+                (unsigned long long)__double_as_longlong(max_rel));
+      atomicMax((unsigned long long*)&fa.stats->max_band,
+                (unsigned long long)__double_as_longlong(max_band));
+      atomicAdd(&fa.stats->sum_rel, sum_rel);
+      atomicAdd(&fa.stats->pairs, pairs);
+    }
+    return;
   }
 
   // ---- a4: sort by (S(p, j), id); drop repeated ids -------------------------
@@ -791,6 +845,30 @@ static hipError_t launch_shape(const GraphView& g, const SweepArgs& a, const F32
   return hipGetLastError();
 }
 
+template <int NB, bool CSUM, bool VEC>
+static hipError_t launch_diag(const GraphView& g, const SweepArgs& a, const F32Args& fa,
+                              DevCounters* ctr, hipStream_t s) {
+  const size_t shmem = Shape<NB>::LDS_B;
+  hipLaunchKernelGGL((prune_f32_kernel<1, NB, CSUM, VEC, true>), dim3((unsigned)fa.n_nodes),
+                     dim3(64), shmem, s, g, a, fa, ctr);
+  return hipGetLastError();
+}
+
+template <bool VEC>
+static hipError_t diag_vec(const GraphView& g, const SweepArgs& a, F32Args& fa, DevCounters* ctr,
+                           hipStream_t s) {
+  if (g.r_max > 64) {
+    f32_bound_constants(g.d, true, &fa.c1, &fa.c2, &fa.c3);
+    return launch_diag<3, true, VEC>(g, a, fa, ctr, s);
+  }
+  if (g.d > 128) {
+    f32_bound_constants(g.d, true, &fa.c1, &fa.c2, &fa.c3);
+    return launch_diag<2, true, VEC>(g, a, fa, ctr, s);
+  }
+  f32_bound_constants(g.d, false, &fa.c1, &fa.c2, &fa.c3);
+  return launch_diag<2, false, VEC>(g, a, fa, ctr, s);
+}
+
 template <bool VEC>
 static hipError_t launch_vec(const GraphView& g, const SweepArgs& a, F32Args& fa,
                              DevCounters* ctr, hipStream_t s) {
@@ -806,10 +884,27 @@ static hipError_t launch_vec(const GraphView& g, const SweepArgs& a, F32Args& fa
   return launch_shape<2, false, VEC>(g, a, fa, ctr, s);
 }
 
+hipError_t launch_gram_error_f32(const GraphView& g, const int32_t* nodes, int64_t n_nodes,
+                                GramErrorStats* stats, DevCounters* ctr, hipStream_t s) {
+  if (n_nodes == 0) return hipSuccess;
+  SweepArgs a = {};
+  a.n_alpha = 1;
+  a.n_out = 0;
+  a.num2[0] = a.den2[0] = 1;
+  a.ratio[0] = 1.0;
+  F32Args fa = {};
+  fa.nr = 0;
+  fa.nodes = nodes;
+  fa.n_nodes = n_nodes;
+  fa.stats = stats;
+  const bool vec = (g.d % 4) == 0 && (((uintptr_t)g.X) & 15) == 0;
+  return vec ? diag_vec<true>(g, a, fa, ctr, s) : diag_vec<false>(g, a, fa, ctr, s);
+}
+
 hipError_t launch_prune_f32(const GraphView& g, const SweepArgs& a_in, DevCounters* ctr,
                             hipStream_t s) {
   if (a_in.n_alpha < 1 || a_in.n_out % a_in.n_alpha != 0) return hipErrorInvalidValue;
-  F32Args fa;
+  F32Args fa = {};
   fa.nr = a_in.n_out / a_in.n_alpha;
   // the kernel takes the alphas in descending order (num_a den_b vs num_b den_a);
   // outputs are alpha-major (o = alpha * nr + iR) and move with their alpha

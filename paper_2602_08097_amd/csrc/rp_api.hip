@@ -304,6 +304,38 @@ void rp_plan_free(rp_plan_t p) {
   delete p;
 }
 
+rp_status rp_gram_error(rp_graph_t g, const int32_t* nodes, int64_t n_nodes, double* out,
+                        void* stream) {
+  if (!g) return fail(RP_ESTATE, "graph is null");
+  if (!out) return fail(RP_EINVAL, "out is null");
+  const rp::GraphView& v = g->view;
+  if (v.dtype != RP_F32 || !rp::prune_f32_supported(v))
+    return fail(RP_EINVAL, "needs a float32 graph with out-lists of at most 96 ids");
+  if (n_nodes < 0 || n_nodes >= (1ll << 31)) return fail(RP_EINVAL, "bad n_nodes");
+  for (int i = 0; i < 4; ++i) out[i] = 0.0;
+  if (n_nodes == 0) return ok();
+  if (!device_range(nodes, (size_t)n_nodes * 4))
+    return fail(RP_EINVAL, "nodes is not a device array of n_nodes int32");
+  hipStream_t s = (hipStream_t)stream;
+  rp::GramErrorStats* d = nullptr;
+  if (hipMalloc((void**)&d, sizeof(*d)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(RP_ENOMEM, "hipMalloc failed");
+  }
+  rp::GramErrorStats h = {};
+  hipError_t e = hipMemcpyAsync(d, &h, sizeof(h), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = rp::launch_gram_error_f32(v, nodes, n_nodes, d, g->ctr, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d);
+  if (e != hipSuccess) return check_launch(e, "gram error");
+  out[0] = h.max_rel;
+  out[1] = h.pairs ? h.sum_rel / (double)h.pairs : 0.0;
+  out[2] = (double)h.pairs;
+  out[3] = h.max_band;
+  return ok();
+}
+
 rp_status rp_tune_set(rp_graph_t g, int32_t n_a, int32_t n_R, int32_t waves) {
   if (!g) return fail(RP_ESTATE, "graph is null");
   if (n_a < 1 || n_a > rp::kMaxAlphas || n_R < 1 || n_R > rp::kMaxRs)

@@ -52,6 +52,14 @@ struct GraphView {
   const float* maxabs;    // max_k |x_k| per point (float32 points; library-owned), else null
 };
 
+// Measured error of the float32 kernel's approximate distances (device).
+struct GramErrorStats {
+  double max_rel;    // max |S~ - S| / S over candidate pairs with S > 0
+  double sum_rel;
+  unsigned long long pairs;
+  double max_band;   // max |S~ - S| / E_j: the proven bound holds while this is <= 1
+};
+
 // One query of a batched search: its row and its outputs (device pointers;
 // dist and hops nullable).
 struct SearchJob {
@@ -70,6 +78,9 @@ hipError_t launch_prune_plain(const GraphView& g, uint32_t num2, uint32_t den2, 
                               hipStream_t s);
 hipError_t launch_prune_batched(const GraphView& g, const SweepArgs& a, DevCounters* ctr,
                                 hipStream_t s);
+hipError_t launch_gram_error_f32(const GraphView& g, const int32_t* nodes, int64_t n_nodes,
+                                 GramErrorStats* stats, DevCounters* ctr, hipStream_t s);
+bool prune_f32_supported(const GraphView& g);
 hipError_t launch_search(const GraphView& g, const void* Q, int64_t nq, int32_t k, int32_t L,
                          int32_t* out_ids, double* out_dist, int32_t* out_hops,
                          hipStream_t s);

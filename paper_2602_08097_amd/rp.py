@@ -60,7 +60,7 @@ REQ_QUERY = 2
 EXPORTS = ["rp_load_graph", "rp_graph_derive", "rp_prune", "rp_prune_sweep", "rp_prune_plain",
            "rp_search", "rp_read_counters", "rp_free_graph", "rp_last_error",
            "rp_plan_sweep", "rp_plan_launch", "rp_plan_free",
-           "rp_autotune_sweep", "rp_tune_set", "rp_tune_get",
+           "rp_autotune_sweep", "rp_tune_set", "rp_tune_get", "rp_gram_error",
            "rp_server_create", "rp_server_submit", "rp_server_poll", "rp_server_replay",
            "rp_server_stats_get", "rp_server_destroy"]
 
@@ -106,6 +106,8 @@ def load_library(path: str = LIB_PATH):
     lib.rp_autotune_sweep.argtypes = [vp, C.POINTER(Alpha), i32, C.POINTER(i32), i32,
                                       C.POINTER(vp), C.POINTER(vp), vp, C.POINTER(i32),
                                       C.POINTER(C.c_float)]
+    lib.rp_gram_error.restype = i32
+    lib.rp_gram_error.argtypes = [vp, vp, i64, C.POINTER(C.c_double), vp]
     lib.rp_tune_set.restype = i32
     lib.rp_tune_set.argtypes = [vp, i32, i32, i32]
     lib.rp_tune_get.restype = i32
@@ -289,6 +291,18 @@ class Graph:
             with open(cache, "w") as f:
                 json.dump(table, f, indent=1, sort_keys=True)
         return res
+
+    def gram_error(self, nodes: torch.Tensor, stream=None) -> dict:
+        """Measured error of the float32 kernel's approximate candidate
+        distances on the listed vertices (see rp_gram_error)."""
+        _need_cuda(nodes)
+        if nodes.dtype != torch.int32:
+            raise TypeError("nodes must be int32")
+        out = (C.c_double * 4)()
+        _check(_lib.rp_gram_error(self.handle, nodes.data_ptr(), nodes.numel(), out,
+                                  _stream_ptr(stream)))
+        return {"max_rel": out[0], "mean_rel": out[1], "pairs": int(out[2]),
+                "max_err_over_bound": out[3]}
 
     def search(self, Q: torch.Tensor, k: int, L: int, want_dist: bool = True, stream=None):
         _need_cuda(Q)

@@ -441,3 +441,37 @@ def test_vertices_per_workgroup_and_autotune(name, n, tmp_path):
     for (a_nb, a_dg), (b_nb, b_dg) in zip(got, ref):
         assert torch.equal(a_nb, b_nb) and torch.equal(a_dg, b_dg)
     rp._check(rp._lib.rp_tune_set(g.handle, na, nr, 0))
+
+
+@pytest.mark.parametrize("name,n", [("deep_f32", 6_000), ("gist_f32", 1_500), ("tiny", 3_000)])
+def test_measured_distance_error_stays_inside_the_proven_band(name, n):
+    """The float32 kernel's approximate candidate distances, measured against
+    canonical FP64 on sampled vertices, never leave the band E_j the kernel
+    uses to decide which pairs need an FP64 recheck."""
+    dev = _dev()
+    w = workloads.build(name, n=n, nq=10, device=dev)
+    spec = w.spec
+    g0 = _graph(w.X, w.knn, w.knn_deg, w.start)
+    nb, dg = g0.prune(spec.base_alpha, spec.base_R)
+    g = g0.derive(nb, dg)
+    nodes = torch.from_numpy(w.sample[:400].astype(np.int32)).to(dev)
+    e = g.gram_error(nodes)
+    assert e["pairs"] > 1000
+    assert 0.0 < e["max_err_over_bound"] <= 1.0, e
+    assert e["max_rel"] < 1e-2 and e["mean_rel"] < 1e-4, e
+
+
+def test_measured_distance_error_wide_dynamic_range():
+    """Rows spanning 12 orders of magnitude and exact duplicates."""
+    dev = _dev()
+    rng = np.random.default_rng(5)
+    n, d = 400, 40
+    X = (rng.integers(-3, 4, (n, d)) * 0.25).astype(np.float32)
+    X[50:60] = (rng.standard_normal((10, d)) * 1e6).astype(np.float32)
+    X[60:70] = (rng.standard_normal((10, d)) * 1e-6).astype(np.float32)
+    X[10:15] = X[7]
+    nbr = rng.integers(0, n, (n, 64)).astype(np.int32)
+    deg = np.full(n, 64, np.int32)
+    g = _graph(X, nbr, deg, 0)
+    e = g.gram_error(torch.arange(n, dtype=torch.int32, device=dev))
+    assert e["pairs"] > 0 and e["max_err_over_bound"] <= 1.0, e
