@@ -1,32 +1,40 @@
 // k_prune_u8.hip -- batched RP-Tuning for uint8 points on int8 MFMA.
 //
 // One wavefront runs RobustPrune(p, N_out(p), alpha, R) (Algorithm 1) for one
-// vertex p at every alpha of a sweep from a single gather of the candidate
+// vertex p at every alpha of a sweep from a single read of the candidate
 // rows.  For out-lists of at most 64 ids and d a multiple of 16 (d <= 256):
 //
-//  a1  read:   lane t holds the t-th listed id.
-//  a2  gather: coalesced 16-byte loads, d/16 consecutive lanes per row, all
-//              of a lane's loads in flight together, stored to LDS as int8
+//  a1  read:   lane t holds the t-th listed id (its slot).
+//  a2  gather: the rows go straight from global memory into the registers
+//              the matrix instruction takes: for row block b (slots
+//              32 b .. 32 b + 31) lane l holds bytes 32 k + 16 (l / 32) .. + 15
+//              of row 32 b + l % 32 for every 32-byte step k -- one 16-byte
+//              load each, all in flight together -- shifted to int8
 //              u = x - 128 (the shift leaves every difference unchanged).
+//              No LDS staging.
 //  a3  p-row:  S(p, j) = |u_p|^2 + |u_j|^2 - 2 <u_p, u_j>, exact in int32,
-//              with 4-way int8 dot products.
-//  a4  sort:   a 64-lane bitonic sort of keys (S(p, j), id, slot) packed in
-//              64 bits, lane exchanges by DPP and swizzles.  The repeated
-//              argmin of Algorithm 1 over a shrinking candidate set visits the
-//              candidates in this order; p and repeated ids are dropped.
+//              with 4-way int8 dot products on the same registers (the two
+//              halves of a row are combined across lanes l and l + 32).
+//  a4  sort:   keys (S(p, j), id, slot) packed in 64 bits.  A list already in
+//              (S, id) order -- every RobustPrune output is -- keeps its rows
+//              where they are; otherwise a 64-lane bitonic sort (DPP and
+//              swizzle exchanges) orders the keys and the rows move to their
+//              ranks by lane permutes.  The repeated argmin of Algorithm 1
+//              over a shrinking candidate set visits the candidates in this
+//              order; p and repeated ids are dropped.
 //  a5  Gram:   G = U U^T over the rank-ordered rows on
-//              v_mfma_i32_32x32x32_i8 (exact int32 accumulation); blocks on
-//              and above the diagonal only; S(i, j) = |u_i|^2 + |u_j|^2
-//              - 2 G(i, j) is written to a 12 KiB LDS tile.
+//              v_mfma_i32_32x32x32_i8 (exact int32 accumulation), one 32 x 32
+//              block at a time, blocks on and above the diagonal only.
 //  a6  test:   alpha * D(p*, p') <= D(p, p') on squares is
 //              num^2 S(p*, p') <= den^2 S(p, p')  <=>  S(p*, p') <= T(p'),
 //              T(p') = floor(den^2 S(p, p') / num^2), exact for integer S.
-//  a7  greedy: per alpha a 64-bit survivor mask; p* = lowest surviving rank
-//              is kept, its S row is read from LDS and one ballot of
-//              S(p*, .) <= T removes p* itself (S = 0) and every candidate it
-//              prunes.  All alphas advance in lockstep without branches, so
-//              their LDS reads are in flight together.  A chain stops at the
-//              largest R requested for its alpha; a smaller R is a prefix.
+//              With the alphas ascending, the alphas that prune p' from p*
+//              are a prefix 0..c-1; the 3 KiB decision tile stores 2^c - 1.
+//  a7  greedy: per alpha a 64-bit survivor mask.  Survivors whose row prunes
+//              nothing at that alpha are kept in runs; each survivor whose row
+//              can prune is kept and one ballot over its tile row removes what
+//              it prunes.  A chain stops at the largest R requested for its
+//              alpha; a smaller R is a prefix.
 //  a8  write:  kept ranks are scattered to their positions (popcount of the
 //              kept ranks before them), -1 padded.
 #include "dev_common.h"
@@ -38,12 +46,9 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 
 namespace {
 
-constexpr int kSTileBytes = 3072;  // count tile, 3 KiB: the blocks on and above the diagonal
+constexpr int kDecisionBytes = 3072;  // decision tile: the blocks on and above the diagonal
 constexpr int kMaxDimU8 = 256;
-constexpr int kGatherBatch = 9;  // 16-byte loads in flight per lane (65 rows x 128 B = 520)
-
-__host__ __device__ constexpr int u_stride(int d) { return d + 16; }
-
+constexpr int kWaveLdsU8 = kDecisionBytes + 64 * 4;  // + |u|^2 by rank
 
 // floor(den2 * s / num2) for s < 2^28, exact: s * fl(den2 / num2) is within
 // 2^-24 of the quotient, so one integer correction step settles it.
@@ -57,27 +62,6 @@ __device__ __forceinline__ int32_t alpha_threshold(uint32_t num2, uint32_t den2,
   return (int32_t)t;
 }
 
-// ---------------------------------------------------------------------------
-// Per-vertex pieces of the kernel.
-// ---------------------------------------------------------------------------
-
-struct Tile {
-  int8_t* U;        // candidate rows (slot order) + x_p, as u = x - 128
-  uint8_t* C;       // count tile (overlays U after the Gram)
-  int32_t* nr;      // |u|^2 by rank
-  int stride;       // bytes per U row
-};
-
-__device__ __forceinline__ Tile make_tile(uint8_t* lds, int d) {
-  Tile t;
-  t.stride = u_stride(d);
-  t.U = (int8_t*)lds;
-  t.C = lds;
-  const int tile_bytes = max(65 * t.stride, kSTileBytes);
-  t.nr = (int32_t*)(lds + tile_bytes);
-  return t;
-}
-
 // a1: the list of p (row and degree loads in flight together).
 __device__ __forceinline__ int load_list(const GraphView& g, int64_t p, int lane) {
   const int raw = lane < g.r_max ? g.nbr[p * g.r_max + lane] : -1;
@@ -85,62 +69,137 @@ __device__ __forceinline__ int load_list(const GraphView& g, int64_t p, int lane
   return lane < m ? raw : -1;
 }
 
-// Chunk c of the gather (c = lane + 64 t): row c / cpr (64 = x_p), 16-byte column c % cpr.
-__device__ __forceinline__ void chunk_pos(int c, int cpr, float inv_cpr, int& row, int& col) {
-  row = (int)(((float)c + 0.5f) * inv_cpr);
-  col = c - row * cpr;
-}
-
 struct Front {
   uint64_t valid_mask;
   int id_rank;
 };
 
-// a3..a6 on rows already in the U tile: p-row, sort, Gram, thresholds and the
-// count tile.  Alphas arrive in ascending order, so their thresholds
-// T_0(j) >= T_1(j) >= ... and the alphas whose test holds for a pair (i, j)
-// are a prefix 0..c-1; the tile stores c(i, j) = #{k : S(i, j) <= T_k(j)} and
-// chain k prunes j from i exactly when c(i, j) > k.
-template <int NA>
-__device__ __forceinline__ Front node_front(const Tile& tl, const SweepArgs& a, int d, int64_t p,
-                                            int id, int lane, int idbits) {
-  const int stride = tl.stride;
-  // ---- a3: p-row S(p, j) and |u_j|^2 -------------------------------------
-  int32_t nj = 0, dotp = 0, np = 0;
-  {
-    const int8_t* uj = tl.U + lane * stride;
-    const int8_t* up = tl.U + 64 * stride;
-    for (int c = 0; c < d; c += 16) {
-      int4 xj = *(const int4*)(uj + c);
-      int4 xp = *(const int4*)(up + c);
-      nj = __builtin_amdgcn_sdot4(xj.x, xj.x, nj, false);
-      nj = __builtin_amdgcn_sdot4(xj.y, xj.y, nj, false);
-      nj = __builtin_amdgcn_sdot4(xj.z, xj.z, nj, false);
-      nj = __builtin_amdgcn_sdot4(xj.w, xj.w, nj, false);
-      dotp = __builtin_amdgcn_sdot4(xj.x, xp.x, dotp, false);
-      dotp = __builtin_amdgcn_sdot4(xj.y, xp.y, dotp, false);
-      dotp = __builtin_amdgcn_sdot4(xj.z, xp.z, dotp, false);
-      dotp = __builtin_amdgcn_sdot4(xj.w, xp.w, dotp, false);
-      np = __builtin_amdgcn_sdot4(xp.x, xp.x, np, false);
-      np = __builtin_amdgcn_sdot4(xp.y, xp.y, np, false);
-      np = __builtin_amdgcn_sdot4(xp.z, xp.z, np, false);
-      np = __builtin_amdgcn_sdot4(xp.w, xp.w, np, false);
-    }
+__device__ __forceinline__ v4i shift_u8(v4i x) {
+  x.x ^= 0x80808080;
+  x.y ^= 0x80808080;
+  x.z ^= 0x80808080;
+  x.w ^= 0x80808080;
+  return x;
+}
+
+__device__ __forceinline__ v4i shfl_v4i(v4i x, int src) {
+  v4i y;
+  y.x = __shfl(x.x, src, 64);
+  y.y = __shfl(x.y, src, 64);
+  y.z = __shfl(x.z, src, 64);
+  y.w = __shfl(x.w, src, 64);
+  return y;
+}
+
+__device__ __forceinline__ int sdot16(v4i a, v4i b, int acc) {
+  acc = __builtin_amdgcn_sdot4(a.x, b.x, acc, false);
+  acc = __builtin_amdgcn_sdot4(a.y, b.y, acc, false);
+  acc = __builtin_amdgcn_sdot4(a.z, b.z, acc, false);
+  acc = __builtin_amdgcn_sdot4(a.w, b.w, acc, false);
+  return acc;
+}
+
+// The decision codes of one 32 x 32 block (rows of block BI, columns of block
+// BJ) from its Gram accumulator; the diagonal blocks keep only columns after
+// the row.  Tile layout: columns 0..31 of rows 0..31 at byte 32 i + c; columns
+// 32..63 of rows 0..63 at byte 1024 + 32 i + (c - 32).  Accumulator layout:
+// lane l holds column l % 32 of rows 8 (v / 4) + 4 (l / 32) + v % 4 in
+// register v.
+template <int NA, int BI, int BJ>
+__device__ __forceinline__ void decide_block(uint8_t* C, const int32_t* nr, const v16i& acc,
+                                             const int32_t (&T)[NA], int l32, int half) {
+  const int32_t ncol = nr[32 * BJ + l32];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int r = 8 * (v >> 2) + 4 * half + (v & 3);
+    const int32_t s = nr[32 * BI + r] + ncol - 2 * acc[v];
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < NA; ++k) c += (uint32_t)(s <= T[k]);
+    asm("" : "+v"(c));  // keep the count 32-bit (carry adds)
+    const uint32_t t = (BI != BJ || l32 > r) ? (1u << c) - 1u : 0u;
+    const int at = BJ == 0 ? r * 32 + l32 : 1024 + (32 * BI + r) * 32 + l32;
+    C[at] = (uint8_t)t;
   }
-  const uint32_t sp = (uint32_t)(np + nj - 2 * dotp);
+}
+
+// a1..a6 for vertex p: rows into registers, p-row, sort, Gram, decision tile.
+template <int NA, int NK>
+__device__ __forceinline__ Front node_front(uint8_t* C, int32_t* nr, const GraphView& g,
+                                            const SweepArgs& a, int64_t p, int lane,
+                                            int idbits) {
+  const int d = g.d;
+  const uint8_t* X = (const uint8_t*)g.X;
+  const int l32 = lane & 31;
+  const int half = lane >> 5;
+
+  // ---- a1 ----------------------------------------------------------------
+  const int id = load_list(g, p, lane);
+  const int usable = (id >= 0 && id != (int)p) ? id : -1;
+  const int id0 = __shfl(usable, l32, 64);        // row of block 0 in this lane
+  const int id1 = __shfl(usable, 32 + l32, 64);   // row of block 1
+
+  // ---- a2: 16-byte slices of every row, straight into registers ----------
+  v4i f0[NK], f1[NK], fp[NK];
+  const v4i zero = {(int)0x80808080, (int)0x80808080, (int)0x80808080, (int)0x80808080};
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    const int off = 32 * k + 16 * half;
+    const bool in = off < d;
+    f0[k] = (in && id0 >= 0) ? *(const v4i*)(X + (int64_t)id0 * d + off) : zero;
+    f1[k] = (in && id1 >= 0) ? *(const v4i*)(X + (int64_t)id1 * d + off) : zero;
+    fp[k] = in ? *(const v4i*)(X + p * d + off) : zero;
+  }
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    f0[k] = shift_u8(f0[k]);
+    f1[k] = shift_u8(f1[k]);
+    fp[k] = shift_u8(fp[k]);
+  }
+
+  // ---- a3: p-row S(p, j) and |u_j|^2 -------------------------------------
+  int n0 = 0, n1 = 0, q0 = 0, q1 = 0, np = 0;
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    n0 = sdot16(f0[k], f0[k], n0);
+    n1 = sdot16(f1[k], f1[k], n1);
+    q0 = sdot16(f0[k], fp[k], q0);
+    q1 = sdot16(f1[k], fp[k], q1);
+    np = sdot16(fp[k], fp[k], np);
+  }
+  n0 += __shfl_xor(n0, 32, 64);
+  n1 += __shfl_xor(n1, 32, 64);
+  q0 += __shfl_xor(q0, 32, 64);
+  q1 += __shfl_xor(q1, 32, 64);
+  np += __shfl_xor(np, 32, 64);
+  // lane l is slot l: block 0 for l < 32, block 1 for l >= 32
+  const int32_t nj = half ? n1 : n0;
+  const uint32_t sp = (uint32_t)(np + nj - 2 * (half ? q1 : q0));
 
   // ---- a4: sort by (S(p, j), id); drop p and repeated ids ---------------
   const uint64_t kInvalid = ~0ull;
   const int shift = idbits + 6;
-  uint64_t key = (id >= 0 && id != (int)p)
+  uint64_t key = usable >= 0
                      ? (((uint64_t)sp << shift) | ((uint64_t)(uint32_t)id << 6) | (uint64_t)lane)
                      : kInvalid;
-  // A list already in (S, id) order -- every RobustPrune output is -- skips
-  // the sorting network.
   uint64_t prev = shfl_u64(key, lane > 0 ? lane - 1 : 0);
   if (__ballot(lane > 0 && key < prev)) {
     key = wave_sort(key, lane);
     prev = shfl_u64(key, lane > 0 ? lane - 1 : 0);
+    // rows to their ranks: row of rank 32 b + l32 comes from slot sl_b,
+    // held by lane (sl_b % 32) + 32 half of block sl_b / 32
+    const int slot = (int)(key & 63);
+    const int sl0 = __shfl(slot, l32, 64);
+    const int sl1 = __shfl(slot, 32 + l32, 64);
+    const int src0 = (sl0 & 31) + 32 * half;
+    const int src1 = (sl1 & 31) + 32 * half;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const v4i a0 = shfl_v4i(f0[k], src0), b0 = shfl_v4i(f1[k], src0);
+      const v4i a1 = shfl_v4i(f0[k], src1), b1 = shfl_v4i(f1[k], src1);
+      f0[k] = sl0 >= 32 ? b0 : a0;
+      f1[k] = sl1 >= 32 ? b1 : a1;
+    }
   }
   {
     const bool dup = lane > 0 && key != kInvalid && (key >> 6) == (prev >> 6);
@@ -152,11 +211,9 @@ __device__ __forceinline__ Front node_front(const Tile& tl, const SweepArgs& a, 
   const int slot = (int)(key & 63);
   const uint32_t s_rank = valid ? (uint32_t)(key >> shift) : 0u;
   f.id_rank = valid ? (int)((key >> 6) & ((1ull << idbits) - 1)) : -1;
-  tl.nr[lane] = __shfl(nj, slot, 64);
+  nr[lane] = __shfl(nj, slot, 64);
 
   // ---- a6: thresholds of this rank, then of the lane's two tile columns ---
-  const int l32 = lane & 31;
-  const int half = lane >> 5;
   int32_t T0[NA], T1[NA];
 #pragma unroll
   for (int k = 0; k < NA; ++k) {
@@ -164,116 +221,112 @@ __device__ __forceinline__ Front node_front(const Tile& tl, const SweepArgs& a, 
     T0[k] = __shfl(t, l32, 64);        // column l32
     T1[k] = __shfl(t, 32 + l32, 64);   // column 32 + l32
   }
+  wave_sync();  // |u|^2 by rank is visible
 
-  // ---- a5: Gram tile on MFMA (rank order) -------------------------------
-  const int sl0 = __shfl(slot, l32, 64);        // row of rank l32
-  const int sl1 = __shfl(slot, 32 + l32, 64);   // row of rank 32 + l32
-  v16i acc00 = {0}, acc01 = {0}, acc11 = {0};
-  const int d32 = (d + 31) & ~31;
-  for (int kk = 0; kk < d32; kk += 32) {
-    const int off = kk + half * 16;
-    v4i f0 = {0, 0, 0, 0}, f1 = {0, 0, 0, 0};
-    if (off < d) {
-      f0 = *(const v4i*)(tl.U + sl0 * stride + off);
-      f1 = *(const v4i*)(tl.U + sl1 * stride + off);
-    }
-    acc00 = __builtin_amdgcn_mfma_i32_32x32x32_i8(f0, f0, acc00, 0, 0, 0);
-    acc01 = __builtin_amdgcn_mfma_i32_32x32x32_i8(f0, f1, acc01, 0, 0, 0);
-    acc11 = __builtin_amdgcn_mfma_i32_32x32x32_i8(f1, f1, acc11, 0, 0, 0);
-  }
-  wave_sync();  // every U read is done before the count tile overwrites it
-
-  // Count tile, 3072 bytes: columns 0..31 of rows 0..31 at byte 32 i + c;
-  // columns 32..63 of rows 0..63 at byte 1024 + 32 i + (c - 32).  Row i is
-  // then read by lane c at byte 32 i + (c % 32) + 1024 (c / 32).
-  // Accumulator layout of a 32 x 32 block: lane l holds column l % 32 of rows
-  // 8 (v / 4) + 4 (l / 32) + v % 4 in register v.
+  // ---- a5: Gram blocks on MFMA (rank order), then their decision codes ----
+  const int nk = (d + 31) >> 5;
   {
-    const int32_t ncol0 = tl.nr[l32];
-    const int32_t ncol1 = tl.nr[32 + l32];
+    v16i acc = {0};
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int r = 8 * (v >> 2) + 4 * half + (v & 3);
-      const int32_t nrow0 = tl.nr[r];
-      const int32_t nrow1 = tl.nr[32 + r];
-      const int32_t s00 = nrow0 + ncol0 - 2 * acc00[v];
-      const int32_t s01 = nrow0 + ncol1 - 2 * acc01[v];
-      const int32_t s11 = nrow1 + ncol1 - 2 * acc11[v];
-      uint32_t c00 = 0, c01 = 0, c11 = 0;
+    for (int k = 0; k < NK; ++k)
+      if (k < nk) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(f0[k], f0[k], acc, 0, 0, 0);
+    decide_block<NA, 0, 0>(C, nr, acc, T0, l32, half);
+  }
+  {
+    v16i acc = {0};
 #pragma unroll
-      for (int k = 0; k < NA; ++k) {
-        c00 += (uint32_t)(s00 <= T0[k]);
-        c01 += (uint32_t)(s01 <= T1[k]);
-        c11 += (uint32_t)(s11 <= T1[k]);
-      }
-      asm("" : "+v"(c00), "+v"(c01), "+v"(c11));  // keep the counts 32-bit (carry adds)
-      tl.C[r * 32 + l32] = (uint8_t)c00;
-      tl.C[1024 + r * 32 + l32] = (uint8_t)c01;
-      tl.C[1024 + (32 + r) * 32 + l32] = (uint8_t)c11;
-    }
+    for (int k = 0; k < NK; ++k)
+      if (k < nk) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(f0[k], f1[k], acc, 0, 0, 0);
+    decide_block<NA, 0, 1>(C, nr, acc, T1, l32, half);
+  }
+  {
+    v16i acc = {0};
+#pragma unroll
+    for (int k = 0; k < NK; ++k)
+      if (k < nk) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(f1[k], f1[k], acc, 0, 0, 0);
+    decide_block<NA, 1, 1>(C, nr, acc, T1, l32, half);
   }
   return f;
 }
 
-// a7 + a8 on the count tile: greedy, outputs of p.
-template <int NA, int NR, bool CAP>
-__device__ __forceinline__ void node_back(const Tile& tl, const SweepArgs& a, int64_t p,
-                                          const Front& f, int lane) {
+// a7 + a8 on the decision tile: greedy, outputs of p.
+template <int NA, bool CAP>
+__device__ __forceinline__ void node_back(const uint8_t* C, const SweepArgs& a, int64_t p,
+                                          const Front& f, int lane, int NR) {
   // ---- a7: greedy keep / discard, all alphas in lockstep ----------------
   // outputs are alpha-major: output ai * NR + ir has alpha ai, bound R_ir
   int rmax[NA];
-  if (CAP) {
 #pragma unroll
-    for (int ai = 0; ai < NA; ++ai) {
+  for (int ai = 0; ai < NA; ++ai) {
+    rmax[ai] = 64;
+    if (CAP) {
       rmax[ai] = 0;
-#pragma unroll
       for (int ir = 0; ir < NR; ++ir) rmax[ai] = max(rmax[ai], a.out[ai * NR + ir].R);
     }
   }
+  // Rows that prune anything, per chain: the OR of row i's codes (lane i).
+  // Columns 0..31 of rows 0..31 are at bytes 32 i ..; columns 32..63 of every
+  // row at 1024 + 32 i ...
+  uint64_t vis[NA];
+  {
+    uint4 r0 = *(const uint4*)(C + 1024 + 32 * lane);
+    uint4 r1 = *(const uint4*)(C + 1024 + 32 * lane + 16);
+    uint32_t acc = r0.x | r0.y | r0.z | r0.w | r1.x | r1.y | r1.z | r1.w;
+    if (lane < 32) {
+      r0 = *(const uint4*)(C + 32 * lane);
+      r1 = *(const uint4*)(C + 32 * lane + 16);
+      acc |= r0.x | r0.y | r0.z | r0.w | r1.x | r1.y | r1.z | r1.w;
+    }
+    acc |= acc >> 16;
+    acc |= acc >> 8;
+#pragma unroll
+    for (int ai = 0; ai < NA; ++ai) vis[ai] = __ballot((acc >> ai) & 1u) & f.valid_mask;
+  }
   uint64_t alive[NA], kept[NA];
-  int cnt[NA];
 #pragma unroll
   for (int ai = 0; ai < NA; ++ai) {
     alive[ai] = f.valid_mask;
     kept[ai] = 0;
-    cnt[ai] = 0;
   }
   const int lbase = (lane & 31) + 1024 * (lane >> 5);
-  // Chain k steps: keep its lowest survivor i, read row i of the count tile,
-  // drop i itself (its count passes every threshold) and what it prunes.
-  // Phase s advances chains s..NA-1 in lockstep while chain s has survivors;
-  // chains are in ascending alpha and usually finish in that order, so the
-  // phases skip most steps of finished chains (a chain that finishes early
-  // only repeats harmless steps on an empty mask).
+  // Chain k: the survivors before the first survivor i whose row can prune
+  // at alpha_k are kept in turn (none removes anything), then i is kept and
+  // row i removes what it prunes; the chain stops at its largest R (trimmed
+  // below).  Chains with larger alpha prune less and visit fewer rows, so
+  // phase s advances chains 0..s while chain s (the largest alpha still
+  // running) has survivors; a finished chain repeats harmless empty steps.
 #pragma unroll
-  for (int s0 = 0; s0 < NA; ++s0) {
-    while (alive[s0] != 0) {
+  for (int s0 = NA - 1; s0 >= 0; --s0) {
+    while (uniform_u64(alive[s0]) != 0) {
       uint32_t row[NA];
 #pragma unroll
-      for (int ai = s0; ai < NA; ++ai) {
-        // s_ff1 gives -1 for an empty mask; clamping to rank 0 then only
-        // re-sets a bit that is already kept, or that the final mask with
-        // the valid ranks removes.
+      for (int ai = 0; ai <= s0; ++ai) {
         const uint64_t al = uniform_u64(alive[ai]);
         int i;
-        asm("s_ff1_i32_b64 %0, %1" : "=s"(i) : "s"(al));
-        i = max(i, 0);
-        uint64_t k = uniform_u64(kept[ai]);
-        asm("s_bitset1_b64 %0, %1" : "+s"(k) : "s"(i));
+        const uint64_t cand = al & vis[ai];
+        asm("s_ff1_i32_b64 %0, %1" : "=s"(i) : "s"(cand));
+        const uint64_t upto = i < 0 ? ~0ull : (2ull << i) - 1ull;  // ranks <= i
+        const uint64_t k = uniform_u64(kept[ai]) | (al & upto);
         kept[ai] = k;
-        if (CAP) {
-          cnt[ai] += al != 0 ? 1 : 0;
-          if (cnt[ai] >= rmax[ai]) alive[ai] = 0;        // stop right after the R-th keep
-        }
-        row[ai] = tl.C[i * 32 + lbase];
+        alive[ai] = (i < 0 || (CAP && __popcll(k) >= rmax[ai])) ? 0ull : al & ~upto;
+        i = max(i, 0);
+        row[ai] = C[i * 32 + lbase];
       }
 #pragma unroll
-      for (int ai = s0; ai < NA; ++ai)
-        alive[ai] &= ~(uint64_t)__ballot(row[ai] > (uint32_t)ai);
+      for (int ai = 0; ai <= s0; ++ai)
+        alive[ai] &= ~(uint64_t)__ballot(row[ai] >= (1u << ai));
     }
   }
+  // a chain that reached its R keeps its first R ranks
 #pragma unroll
-  for (int ai = 0; ai < NA; ++ai) kept[ai] &= f.valid_mask;
+  for (int ai = 0; ai < NA; ++ai) {
+    const uint64_t k = kept[ai];
+    if (CAP && __popcll(k) > rmax[ai]) {
+      const int before = (int)__builtin_amdgcn_mbcnt_hi(
+          (uint32_t)(k >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)k, 0u));
+      kept[ai] = __ballot(((k >> lane) & 1ull) && before < rmax[ai]);
+    }
+  }
 
   // ---- a8: write every output -------------------------------------------
 #pragma unroll
@@ -282,7 +335,6 @@ __device__ __forceinline__ void node_back(const Tile& tl, const SweepArgs& a, in
     const int tot = __popcll(km);
     const bool mine = (km >> lane) & 1ull;
     const int pos = __popcll(km & ((1ull << lane) - 1ull));
-#pragma unroll
     for (int ir = 0; ir < NR; ++ir) {
       const SweepOut& out = a.out[ai * NR + ir];
       const int R = out.R;
@@ -295,63 +347,22 @@ __device__ __forceinline__ void node_back(const Tile& tl, const SweepArgs& a, in
   }
 }
 
-// One wavefront per vertex (any d multiple of 16 up to 256), blockDim.x / 64
+// One wavefront per vertex (any d multiple of 16 up to 32 NK), blockDim.x / 64
 // vertices per workgroup, each wavefront with its own `wave_lds` bytes of LDS.
-template <int NA, int NR, bool CAP>
+template <int NA, bool CAP, int NK>
 __global__ __launch_bounds__(512) void prune_u8_kernel(GraphView g, SweepArgs a, int32_t idbits,
-                                                       int32_t wave_lds) {
+                                                       int32_t nr_out, int32_t wave_lds) {
   extern __shared__ __align__(16) uint8_t lds_all[];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
   if (p >= g.n) return;
   uint8_t* lds = lds_all + (size_t)wave * wave_lds;
-  const int d = g.d;
-  const Tile tl = make_tile(lds, d);
-  int32_t* idl = tl.nr + 64;  // listed ids by slot, then p
-  const uint8_t* X = (const uint8_t*)g.X;
-
-  const int id = load_list(g, p, lane);
-  idl[lane] = id;
-  if (lane == 0) idl[64] = (int)p;
-  wave_sync();
-
-  // ---- a2: coalesced gather into LDS (u = x - 128) -----------------------
-  // Every load of a batch is issued before any of its stores.
-  {
-    const int cpr = d >> 4;
-    const int total = 65 * cpr;
-    const float inv_cpr = 1.0f / (float)cpr;
-    for (int base = 0; base < total; base += 64 * kGatherBatch) {
-      uint4 buf[kGatherBatch];
-      int dst[kGatherBatch];
-#pragma unroll
-      for (int t = 0; t < kGatherBatch; ++t) {
-        const int c = base + lane + 64 * t;
-        buf[t] = make_uint4(0x80808080u, 0x80808080u, 0x80808080u, 0x80808080u);
-        dst[t] = -1;
-        if (c < total) {
-          int row, col;
-          chunk_pos(c, cpr, inv_cpr, row, col);
-          const int rid = idl[row];
-          dst[t] = row * tl.stride + col * 16;
-          if (rid >= 0) buf[t] = *(const uint4*)(X + (int64_t)rid * d + col * 16);
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < kGatherBatch; ++t) {
-        if (dst[t] >= 0) {
-          uint4 v = buf[t];
-          v.x ^= 0x80808080u; v.y ^= 0x80808080u; v.z ^= 0x80808080u; v.w ^= 0x80808080u;
-          *(uint4*)(tl.U + dst[t]) = v;
-        }
-      }
-    }
-  }
-  wave_sync();
-  const Front f = node_front<NA>(tl, a, d, p, id, lane, idbits);
-  wave_sync();
-  node_back<NA, NR, CAP>(tl, a, p, f, lane);
+  uint8_t* C = lds;                                 // decision tile
+  int32_t* nr = (int32_t*)(lds + kDecisionBytes);  // |u|^2 by rank
+  const Front f = node_front<NA, NK>(C, nr, g, a, p, lane, idbits);
+  wave_sync();  // the decision tile is visible
+  node_back<NA, CAP>(C, a, p, f, lane, nr_out);
 }
 
 struct Launch {
@@ -360,42 +371,36 @@ struct Launch {
   int waves;     // vertices per workgroup
 };
 
-template <int NA, int NR>
-hipError_t launch_nr(const GraphView& g, const SweepArgs& a, const Launch& L, hipStream_t s) {
+template <int NA, int NK>
+hipError_t launch_nk(const GraphView& g, const SweepArgs& a, const Launch& L, hipStream_t s) {
   bool cap = false;
   for (int o = 0; o < a.n_out; ++o) cap = cap || a.out[o].R < g.r_max;
+  const int nr_out = a.n_out / NA;
   const dim3 grid((unsigned)((g.n + L.waves - 1) / L.waves)), block(64 * L.waves);
   const size_t shmem = (size_t)L.wave_lds * L.waves;
   if (cap)
-    hipLaunchKernelGGL((prune_u8_kernel<NA, NR, true>), grid, block, shmem, s, g, a, L.idbits,
-                       L.wave_lds);
+    hipLaunchKernelGGL((prune_u8_kernel<NA, true, NK>), grid, block, shmem, s, g, a, L.idbits,
+                       nr_out, L.wave_lds);
   else
-    hipLaunchKernelGGL((prune_u8_kernel<NA, NR, false>), grid, block, shmem, s, g, a, L.idbits,
-                       L.wave_lds);
+    hipLaunchKernelGGL((prune_u8_kernel<NA, false, NK>), grid, block, shmem, s, g, a, L.idbits,
+                       nr_out, L.wave_lds);
   return hipGetLastError();
 }
 
 template <int NA>
 hipError_t launch_na(const GraphView& g, const SweepArgs& a, const Launch& L, hipStream_t s) {
-  switch (a.n_out / NA) {
-    case 1: return launch_nr<NA, 1>(g, a, L, s);
-    case 2: return launch_nr<NA, 2>(g, a, L, s);
-    case 3: return launch_nr<NA, 3>(g, a, L, s);
-    case 4: return launch_nr<NA, 4>(g, a, L, s);
-    default: return hipErrorInvalidValue;
-  }
+  if (a.n_out % NA != 0 || a.n_out / NA > kMaxRs) return hipErrorInvalidValue;
+  return g.d <= 128 ? launch_nk<NA, 4>(g, a, L, s) : launch_nk<NA, 8>(g, a, L, s);
 }
 
 }  // namespace
 
-int prune_u8_wave_lds(const GraphView& g) {
-  const int stride = u_stride(g.d);
-  return (max(65 * stride, kSTileBytes) + (64 + 68) * (int)sizeof(int32_t) + 15) & ~15;
-}
+int prune_u8_wave_lds(const GraphView&) { return kWaveLdsU8; }
 
+// 16-byte row slices need d % 16 == 0 and a 16-byte aligned point array.
 bool prune_u8_supported(const GraphView& g) {
   return g.dtype == RP_U8 && g.r_max <= 64 && (g.d % 16) == 0 && g.d <= kMaxDimU8 &&
-         g.n <= (1ll << 30);
+         g.n <= (1ll << 30) && (((uintptr_t)g.X) & 15) == 0;
 }
 
 hipError_t launch_prune_u8(const GraphView& g, const SweepArgs& a_in, DevCounters* ctr,
