@@ -94,19 +94,20 @@ def summarize_profile(root):
         if "prune_u8_kernel" in name:
             prune_avg_ns = avg
     res = {"prune_u8_avg_ns": prune_avg_ns}
-    for tag, counter in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
+    for tag in sorted(os.listdir(root)):
+        if tag in ("trace", "summary") or not os.path.isdir(os.path.join(root, tag)):
+            continue
         rows = _read_csvs(os.path.join(root, tag), "counter_collection.csv")
         per = {}
         for r in rows:
-            if _col(r, "Counter_Name", "COUNTER_NAME") != counter:
-                continue
+            counter = _col(r, "Counter_Name", "COUNTER_NAME")
             name = _col(r, "Kernel_Name", "KERNEL_NAME")
             disp = _col(r, "Dispatch_Id", "DISPATCH_ID")
-            per.setdefault(name, {}).setdefault(disp, 0.0)
-            per[name][disp] += float(_col(r, "Counter_Value", "COUNTER_VALUE"))
-        for name, d in per.items():
+            per.setdefault((counter, name), {}).setdefault(disp, 0.0)
+            per[(counter, name)][disp] += float(_col(r, "Counter_Value", "COUNTER_VALUE"))
+        for (counter, name), d in sorted(per.items()):
             vals = list(d.values())
-            res[f"{tag} KiB/dispatch (n={len(vals)}): {name[:100]}"] = sum(vals) / len(vals)
+            res[f"{counter} per dispatch (n={len(vals)}): {name[:100]}"] = sum(vals) / len(vals)
     with open(os.path.join(out, "kernel_stats.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
     with open(os.path.join(out, "counters.json"), "w") as f:

@@ -109,15 +109,21 @@ template <int NA, int BI, int BJ>
 __device__ __forceinline__ void decide_block(uint8_t* C, const int32_t* nr, const v16i& acc,
                                              const int32_t (&T)[NA], int l32, int half) {
   const int32_t ncol = nr[32 * BJ + l32];
+  // |u|^2 of this lane's 16 rows: rows 8 q + 4 half + 0..3 are consecutive
+  int4 nrow[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) nrow[q] = *(const int4*)(nr + 32 * BI + 8 * q + 4 * half);
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
     const int r = 8 * (v >> 2) + 4 * half + (v & 3);
-    const int32_t s = nr[32 * BI + r] + ncol - 2 * acc[v];
-    uint32_t c = 0;
+    const int4 nq = nrow[v >> 2];
+    const int32_t nrv = (v & 3) == 0 ? nq.x : (v & 3) == 1 ? nq.y : (v & 3) == 2 ? nq.z : nq.w;
+    const int32_t s = nrv + ncol - 2 * acc[v];
+    // S exceeds T_k exactly when T_k - S is negative (|S|, |T_k| < 2^24)
+    uint32_t over = 0;
 #pragma unroll
-    for (int k = 0; k < NA; ++k) c += (uint32_t)(s <= T[k]);
-    asm("" : "+v"(c));  // keep the count 32-bit (carry adds)
-    const uint32_t t = (BI != BJ || l32 > r) ? (1u << c) - 1u : 0u;
+    for (int k = 0; k < NA; ++k) over += (uint32_t)(T[k] - s) >> 31;
+    const uint32_t t = (BI != BJ || l32 > r) ? (1u << (NA - over)) - 1u : 0u;
     const int at = BJ == 0 ? r * 32 + l32 : 1024 + (32 * BI + r) * 32 + l32;
     C[at] = (uint8_t)t;
   }
@@ -140,21 +146,27 @@ __device__ __forceinline__ Front node_front(uint8_t* C, int32_t* nr, const Graph
   const int id1 = __shfl(usable, 32 + l32, 64);   // row of block 1
 
   // ---- a2: 16-byte slices of every row, straight into registers ----------
+  // every load reads valid memory (absent rows read x_p, slices past d read
+  // the row's last 16 bytes) and is issued unconditionally; absent data is
+  // zeroed afterwards
   v4i f0[NK], f1[NK], fp[NK];
-  const v4i zero = {(int)0x80808080, (int)0x80808080, (int)0x80808080, (int)0x80808080};
+  const uint8_t* r0 = X + (int64_t)(id0 >= 0 ? id0 : (int)p) * d;
+  const uint8_t* r1 = X + (int64_t)(id1 >= 0 ? id1 : (int)p) * d;
+  const uint8_t* rp = X + p * d;
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
-    const int off = 32 * k + 16 * half;
-    const bool in = off < d;
-    f0[k] = (in && id0 >= 0) ? *(const v4i*)(X + (int64_t)id0 * d + off) : zero;
-    f1[k] = (in && id1 >= 0) ? *(const v4i*)(X + (int64_t)id1 * d + off) : zero;
-    fp[k] = in ? *(const v4i*)(X + p * d + off) : zero;
+    const int off = min(32 * k + 16 * half, d - 16);
+    f0[k] = *(const v4i*)(r0 + off);
+    f1[k] = *(const v4i*)(r1 + off);
+    fp[k] = *(const v4i*)(rp + off);
   }
+  const v4i zero = {0, 0, 0, 0};
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
-    f0[k] = shift_u8(f0[k]);
-    f1[k] = shift_u8(f1[k]);
-    fp[k] = shift_u8(fp[k]);
+    const bool in = 32 * k + 16 * half < d;
+    f0[k] = (in && id0 >= 0) ? shift_u8(f0[k]) : zero;
+    f1[k] = (in && id1 >= 0) ? shift_u8(f1[k]) : zero;
+    fp[k] = in ? shift_u8(fp[k]) : zero;
   }
 
   // ---- a3: p-row S(p, j) and |u_j|^2 -------------------------------------
@@ -305,12 +317,13 @@ __device__ __forceinline__ void node_back(const uint8_t* C, const SweepArgs& a, 
         int i;
         const uint64_t cand = al & vis[ai];
         asm("s_ff1_i32_b64 %0, %1" : "=s"(i) : "s"(cand));
-        const uint64_t upto = i < 0 ? ~0ull : (2ull << i) - 1ull;  // ranks <= i
-        const uint64_t k = uniform_u64(kept[ai]) | (al & upto);
+        // ranks above i; with no candidate (i = -1, shift 63) none, so every
+        // survivor is kept and the chain ends
+        const uint64_t above = 0xFFFFFFFFFFFFFFFEull << (i & 63);
+        const uint64_t k = uniform_u64(kept[ai]) | (al & ~above);
         kept[ai] = k;
-        alive[ai] = (i < 0 || (CAP && __popcll(k) >= rmax[ai])) ? 0ull : al & ~upto;
-        i = max(i, 0);
-        row[ai] = C[i * 32 + lbase];
+        alive[ai] = (CAP && __popcll(k) >= rmax[ai]) ? 0ull : al & above;
+        row[ai] = C[(i & 63) * 32 + lbase];
       }
 #pragma unroll
       for (int ai = 0; ai <= s0; ++ai)
