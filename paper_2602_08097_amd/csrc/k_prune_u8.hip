@@ -106,26 +106,33 @@ __device__ __forceinline__ int sdot16(v4i a, v4i b, int acc) {
 // lane l holds column l % 32 of rows 8 (v / 4) + 4 (l / 32) + v % 4 in
 // register v.
 template <int NA, int BI, int BJ>
-__device__ __forceinline__ void decide_block(uint8_t* C, const int32_t* nr, const v16i& acc,
+__device__ __forceinline__ void decide_block(uint8_t* C, const int32_t* mnr, const v16i& acc,
                                              const int32_t (&T)[NA], int l32, int half) {
-  const int32_t ncol = nr[32 * BJ + l32];
-  // |u|^2 of this lane's 16 rows: rows 8 q + 4 half + 0..3 are consecutive
+  // S(i, j) <= T_k(j)  <=>  y = 2 G(i, j) - |u_i|^2 >= U_k = |u_j|^2 - T_k(j);
+  // |y|, |U_k| < 2^26, so y - U_k does not overflow and its sign bit is
+  // [y < U_k]
+  const int32_t ncol = -mnr[32 * BJ + l32];
+  int32_t U[NA];
+#pragma unroll
+  for (int k = 0; k < NA; ++k) U[k] = ncol - T[k];
+  // -|u|^2 of this lane's 16 rows: rows 8 q + 4 half + 0..3 are consecutive
   int4 nrow[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) nrow[q] = *(const int4*)(nr + 32 * BI + 8 * q + 4 * half);
+  for (int q = 0; q < 4; ++q) nrow[q] = *(const int4*)(mnr + 32 * BI + 8 * q + 4 * half);
+  // row r = 8 q + 4 half + j of the block is byte base + 32 (8 q + j)
+  uint8_t* base = C + (BJ == 0 ? 0 : 1024 + 32 * 32 * BI) + 128 * half + l32;
+  const int below = l32 - 4 * half;  // column after row  <=>  below > 8 q + j
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
-    const int r = 8 * (v >> 2) + 4 * half + (v & 3);
+    const int rr = 8 * (v >> 2) + (v & 3);  // r - 4 half, a constant
     const int4 nq = nrow[v >> 2];
-    const int32_t nrv = (v & 3) == 0 ? nq.x : (v & 3) == 1 ? nq.y : (v & 3) == 2 ? nq.z : nq.w;
-    const int32_t s = nrv + ncol - 2 * acc[v];
-    // S exceeds T_k exactly when T_k - S is negative (|S|, |T_k| < 2^24)
-    uint32_t over = 0;
+    const int32_t mn = (v & 3) == 0 ? nq.x : (v & 3) == 1 ? nq.y : (v & 3) == 2 ? nq.z : nq.w;
+    const int32_t y = 2 * acc[v] + mn;
+    uint32_t over = 0;  // sign bits of y - U_k, no carry flags (no hazard stalls)
 #pragma unroll
-    for (int k = 0; k < NA; ++k) over += (uint32_t)(T[k] - s) >> 31;
-    const uint32_t t = (BI != BJ || l32 > r) ? (1u << (NA - over)) - 1u : 0u;
-    const int at = BJ == 0 ? r * 32 + l32 : 1024 + (32 * BI + r) * 32 + l32;
-    C[at] = (uint8_t)t;
+    for (int k = 0; k < NA; ++k) over += (uint32_t)(y - U[k]) >> 31;
+    const uint32_t t = (BI != BJ || below > rr) ? (1u << (NA - over)) - 1u : 0u;
+    base[32 * rr] = (uint8_t)t;
   }
 }
 
@@ -147,8 +154,7 @@ __device__ __forceinline__ Front node_front(uint8_t* C, int32_t* nr, const Graph
 
   // ---- a2: 16-byte slices of every row, straight into registers ----------
   // every load reads valid memory (absent rows read x_p, slices past d read
-  // the row's last 16 bytes) and is issued unconditionally; absent data is
-  // zeroed afterwards
+  // the row's last 16 bytes) and is issued unconditionally
   v4i f0[NK], f1[NK], fp[NK];
   const uint8_t* r0 = X + (int64_t)(id0 >= 0 ? id0 : (int)p) * d;
   const uint8_t* r1 = X + (int64_t)(id1 >= 0 ? id1 : (int)p) * d;
@@ -160,13 +166,23 @@ __device__ __forceinline__ Front node_front(uint8_t* C, int32_t* nr, const Graph
     f1[k] = *(const v4i*)(r1 + off);
     fp[k] = *(const v4i*)(rp + off);
   }
-  const v4i zero = {0, 0, 0, 0};
+  // (rows of absent slots hold x_p: their sort keys are invalid, and the codes
+  // they produce only ever meet dead survivors)
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
-    const bool in = 32 * k + 16 * half < d;
-    f0[k] = (in && id0 >= 0) ? shift_u8(f0[k]) : zero;
-    f1[k] = (in && id1 >= 0) ? shift_u8(f1[k]) : zero;
-    fp[k] = in ? shift_u8(fp[k]) : zero;
+    f0[k] = shift_u8(f0[k]);
+    f1[k] = shift_u8(f1[k]);
+    fp[k] = shift_u8(fp[k]);
+  }
+  if (d != 32 * NK) {  // uniform: zero the slices past d
+    const v4i zero = {0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const bool in = 32 * k + 16 * half < d;
+      f0[k] = in ? f0[k] : zero;
+      f1[k] = in ? f1[k] : zero;
+      fp[k] = in ? fp[k] : zero;
+    }
   }
 
   // ---- a3: p-row S(p, j) and |u_j|^2 -------------------------------------
@@ -223,7 +239,7 @@ __device__ __forceinline__ Front node_front(uint8_t* C, int32_t* nr, const Graph
   const int slot = (int)(key & 63);
   const uint32_t s_rank = valid ? (uint32_t)(key >> shift) : 0u;
   f.id_rank = valid ? (int)((key >> 6) & ((1ull << idbits) - 1)) : -1;
-  nr[lane] = __shfl(nj, slot, 64);
+  nr[lane] = -__shfl(nj, slot, 64);  // -|u|^2 by rank
 
   // ---- a6: thresholds of this rank, then of the lane's two tile columns ---
   int32_t T0[NA], T1[NA];
@@ -233,7 +249,7 @@ __device__ __forceinline__ Front node_front(uint8_t* C, int32_t* nr, const Graph
     T0[k] = __shfl(t, l32, 64);        // column l32
     T1[k] = __shfl(t, 32 + l32, 64);   // column 32 + l32
   }
-  wave_sync();  // |u|^2 by rank is visible
+  wave_sync();  // the |u|^2 table is visible
 
   // ---- a5: Gram blocks on MFMA (rank order), then their decision codes ----
   const int nk = (d + 31) >> 5;
@@ -372,7 +388,7 @@ __global__ __launch_bounds__(512) void prune_u8_kernel(GraphView g, SweepArgs a,
   if (p >= g.n) return;
   uint8_t* lds = lds_all + (size_t)wave * wave_lds;
   uint8_t* C = lds;                                 // decision tile
-  int32_t* nr = (int32_t*)(lds + kDecisionBytes);  // |u|^2 by rank
+  int32_t* nr = (int32_t*)(lds + kDecisionBytes);  // -|u|^2 by rank
   const Front f = node_front<NA, NK>(C, nr, g, a, p, lane, idbits);
   wave_sync();  // the decision tile is visible
   node_back<NA, CAP>(C, a, p, f, lane, nr_out);
