@@ -154,7 +154,7 @@ def batched_kernel_name(dtype, r_max, d):
     if dtype == np.uint8:
         return "prune_u8_kernel" if r_max <= 64 and d % 16 == 0 and d <= 256 else \
             "prune_plain_kernel"
-    return "prune_f32_kernel" if r_max <= 64 else "prune_plain_kernel"
+    return "prune_f32_kernel" if r_max <= 96 else "prune_plain_kernel"
 
 
 def exact_gt_u8(X, Q, k, chunk=1024):
