@@ -34,16 +34,12 @@
 //              kept, row i of S~ is compared with each lane's thresholds;
 //              the chains of all alphas advance in lockstep.
 //  a8  write:  kept ranks are scattered to their positions, -1 padded.
-#include "dev_common.h"
+#include "f32_common.h"
 
 namespace rp {
 
-typedef _Float16 v8h __attribute__((ext_vector_type(8)));
-typedef float v16f __attribute__((ext_vector_type(16)));
-
 namespace {
 
-constexpr int kDC = 32;         // dimensions per streamed chunk
 constexpr int kRowF = kDC + 4;  // floats per LDS chunk row (16-byte aligned rows)
 
 template <int NB>
@@ -59,72 +55,6 @@ struct Shape {
   static constexpr int A_B = TILE_B > STILE_B ? TILE_B : STILE_B;
   static constexpr int LDS_B = (A_B + MS * 4 + MS * 4 + 15) & ~15;
 };
-
-struct F32Args {
-  double c1, c2, c3;  // rounding band of S~ (scaled units)
-  int32_t nr;         // outputs per alpha (outputs are alpha-major)
-  // measurement mode: only the listed vertices, S~ compared with canonical FP64
-  const int32_t* nodes;
-  int64_t n_nodes;
-  GramErrorStats* stats;
-};
-
-// Next float toward -inf / +inf (finite inputs).
-__device__ __forceinline__ float next_down(float f) {
-  if (f == 0.f) return -1.401298464e-45f;
-  const int b = __float_as_int(f);
-  return __int_as_float(f > 0.f ? b - 1 : b + 1);
-}
-
-__device__ __forceinline__ float next_up(float f) {
-  if (f == 0.f) return 1.401298464e-45f;
-  const int b = __float_as_int(f);
-  return __int_as_float(f > 0.f ? b + 1 : b - 1);
-}
-
-// FP32 value <= x (round down) and >= x (round up).
-__device__ __forceinline__ float f32_down(double x) {
-  float f = (float)x;
-  if ((double)f > x) f = next_down(f);
-  return f;
-}
-
-__device__ __forceinline__ float f32_up(double x) {
-  float f = (float)x;
-  if ((double)f < x) f = next_up(f);
-  return f;
-}
-
-// Canonical FP64 squared distance of two float32 rows in global memory.
-template <bool VEC>
-__device__ __forceinline__ double canon_rows(const float* __restrict__ a,
-                                             const float* __restrict__ b, int d) {
-  double acc = 0.0;
-  int k = 0;
-  if (VEC) {
-    for (; k + 4 <= d; k += 4) {
-      const float4 x = *(const float4*)(a + k);
-      const float4 y = *(const float4*)(b + k);
-      double t = (double)x.x - (double)y.x;
-      acc = __fma_rn(t, t, acc);
-      t = (double)x.y - (double)y.y;
-      acc = __fma_rn(t, t, acc);
-      t = (double)x.z - (double)y.z;
-      acc = __fma_rn(t, t, acc);
-      t = (double)x.w - (double)y.w;
-      acc = __fma_rn(t, t, acc);
-    }
-  }
-  for (; k < d; ++k) {
-    const double t = (double)a[k] - (double)b[k];
-    acc = __fma_rn(t, t, acc);
-  }
-  return acc;
-}
-
-__device__ __forceinline__ bool key_less(uint64_t ah, uint32_t al, uint64_t bh, uint32_t bl) {
-  return ah < bh || (ah == bh && al < bl);
-}
 
 // Sort of up to 128 (hi, lo) keys held two per lane (a: ranks 0..63 after the
 // call, b: ranks 64..127): each half is sorted, b is reversed so a ++ b is
@@ -157,13 +87,6 @@ __device__ __forceinline__ void wave_sort128(uint64_t& ah, uint32_t& al, uint64_
   bitonic_step2<64, 4>(bh, bl, lane);
   bitonic_step2<64, 2>(bh, bl, lane);
   bitonic_step2<64, 1>(bh, bl, lane);
-}
-
-__device__ __forceinline__ int ff1_u64(uint64_t v) {
-  const uint64_t u = uniform_u64(v);
-  int i;
-  asm("s_ff1_i32_b64 %0, %1" : "=s"(i) : "s"(u));
-  return i;  // -1 for an empty mask
 }
 
 // DIAG: measure instead of prune -- for the listed vertices, every candidate
@@ -217,12 +140,7 @@ __global__ __launch_bounds__(512) void prune_f32_kernel(GraphView g, SweepArgs a
     if (idw[w] >= 0) mj = fmaxf(mj, g.maxabs[idw[w]]);
   for (int off = 32; off > 0; off >>= 1) mj = fmaxf(mj, __shfl_xor(mj, off, 64));
   const float bound = mj + g.maxabs[p];
-  int e = 0;
-  if (bound > 0.f) {
-    int ex;
-    frexpf(bound, &ex);
-    e = min(100, max(-100, 14 - ex));
-  }
+  const int e = frame_exponent(bound);
   const float scf = ldexpf(1.f, e);
   const double sc = ldexp(1.0, e);
   const double sc2 = sc * sc;
@@ -777,44 +695,22 @@ __global__ __launch_bounds__(512) void prune_f32_kernel(GraphView g, SweepArgs a
 
 }  // namespace
 
+// the register-streaming kernel (k_prune_f32_reg.hip) for out-lists of at most
+// 64 ids with 16-byte row slices; this one for the other shapes
+bool prune_f32r_supported(const GraphView& g);
+int prune_f32r_wave_lds(const GraphView& g);
+hipError_t launch_prune_f32r(const GraphView& g, const SweepArgs& a, F32Args fa,
+                             DevCounters* ctr, hipStream_t s);
+hipError_t launch_gram_error_f32r(const GraphView& g, const SweepArgs& a, F32Args fa,
+                                  DevCounters* ctr, hipStream_t s);
+
 int prune_f32_wave_lds(const GraphView& g) {
+  if (prune_f32r_supported(g)) return prune_f32r_wave_lds(g);
   return g.r_max > 64 ? Shape<3>::LDS_B : Shape<2>::LDS_B;
 }
 
 bool prune_f32_supported(const GraphView& g) {
   return g.dtype == RP_F32 && g.r_max <= 96 && g.n <= (1ll << 25) && g.maxabs != nullptr;
-}
-
-// Bound of |S~ - S(i, j) 2^2e| for every rank i before j (S(p, i) <= S(p, j)),
-// s = S(p, j) 2^2e, U = (x - x_p) 2^e exact:
-//   e1 = 2^-22 + 2^-23  relative error of hi + lo against U (FP32 subtraction
-//                       2^-24, rounding of lo 2^-22);
-//   ea = 2^-14          absolute error of one element whose hi or lo is an
-//                       FP16 subnormal, even if the matrix unit flushes it;
-//   dropped lo lo'      <= 2^-22 (1 + 2^-9) s;
-//   FP32 accumulation   gamma over the additions into one accumulator, with
-//                       unit 2^-23 (covers truncating hardware), plus the
-//                       gamma of the chunk sums (unit 2^-24);
-//   |G~ - G| <= (2 e1 + e1^2 + lo lo' + acc) s + 2 ea sqrt(d) (1 + e1)(1 + acc) sqrt(s)
-//               + d ea^2 (1 + acc);
-//   S~ = (S(p,i) + S(p,j)) 2^2e - 2 G~ in FP32 adds 8 * 2^-24 s, and the
-//   canonical FP64 values differ from the exact ones by at most 12 d 2^-53 s.
-// Every coefficient is doubled; the FP64 threshold's own rounding is covered
-// by the (1 -/+ 2^-50) factors.
-static void f32_bound_constants(int d, bool csum, double* c1, double* c2, double* c3) {
-  auto gam = [](double n, double u) { return n * u / (1.0 - n * u); };
-  const double u24 = 0x1p-24;
-  const double e1 = 0x1p-22 + 0x1p-23;
-  const double ea = 0x1p-14;
-  const double nadd = csum ? 3.0 * kDC + 1.0 : 3.0 * d + 1.0;
-  const double g1 = gam(nadd, 0x1p-23);
-  const double g2 = csum ? gam((double)((d + kDC - 1) / kDC), u24) : 0.0;
-  const double acc = (g1 + g2 + g1 * g2) * (1.0 + 0x1p-9);
-  const double lolo = 0x1p-22 * (1.0 + 0x1p-9);
-  const double sd = sqrt((double)d);
-  *c1 = 2.0 * (2.0 * (2.0 * e1 + e1 * e1 + lolo + acc) + 8.0 * u24 + 12.0 * d * 0x1p-53);
-  *c2 = 2.0 * (2.0 * 2.0 * ea * sd * (1.0 + e1) * (1.0 + acc));
-  *c3 = 2.0 * (2.0 * d * ea * ea * (1.0 + acc));
 }
 
 template <int NB, bool CSUM, bool VEC>
@@ -897,6 +793,7 @@ hipError_t launch_gram_error_f32(const GraphView& g, const int32_t* nodes, int64
   fa.nodes = nodes;
   fa.n_nodes = n_nodes;
   fa.stats = stats;
+  if (prune_f32r_supported(g)) return launch_gram_error_f32r(g, a, fa, ctr, s);
   const bool vec = (g.d % 4) == 0 && (((uintptr_t)g.X) & 15) == 0;
   return vec ? diag_vec<true>(g, a, fa, ctr, s) : diag_vec<false>(g, a, fa, ctr, s);
 }
@@ -906,30 +803,9 @@ hipError_t launch_prune_f32(const GraphView& g, const SweepArgs& a_in, DevCounte
   if (a_in.n_alpha < 1 || a_in.n_out % a_in.n_alpha != 0) return hipErrorInvalidValue;
   F32Args fa = {};
   fa.nr = a_in.n_out / a_in.n_alpha;
-  // the kernel takes the alphas in descending order (num_a den_b vs num_b den_a);
-  // outputs are alpha-major (o = alpha * nr + iR) and move with their alpha
-  SweepArgs a = a_in;
-  int order[kMaxAlphas];
-  for (int i = 0; i < a_in.n_alpha; ++i) order[i] = i;
-  for (int i = 1; i < a_in.n_alpha; ++i) {
-    const int v = order[i];
-    int j = i - 1;
-    while (j >= 0 && (uint64_t)a_in.num2[v] * a_in.den2[order[j]] >
-                         (uint64_t)a_in.num2[order[j]] * a_in.den2[v]) {
-      order[j + 1] = order[j];
-      --j;
-    }
-    order[j + 1] = v;
-  }
-  for (int k = 0; k < a_in.n_alpha; ++k) {
-    a.num2[k] = a_in.num2[order[k]];
-    a.den2[k] = a_in.den2[order[k]];
-    a.ratio[k] = a_in.ratio[order[k]];
-    for (int ir = 0; ir < fa.nr; ++ir) {
-      a.out[k * fa.nr + ir] = a_in.out[order[k] * fa.nr + ir];
-      a.out[k * fa.nr + ir].alpha_idx = k;
-    }
-  }
+  // the kernel takes the alphas in descending order
+  const SweepArgs a = alphas_descending(a_in, fa.nr);
+  if (prune_f32r_supported(g)) return launch_prune_f32r(g, a, fa, ctr, s);
   const bool vec = (g.d % 4) == 0 && (((uintptr_t)g.X) & 15) == 0;
   return vec ? launch_vec<true>(g, a, fa, ctr, s) : launch_vec<false>(g, a, fa, ctr, s);
 }
