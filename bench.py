@@ -147,6 +147,37 @@ def algorithmic_bytes(deg, d, esz, Rs_per_output):
     return int((4 * (m + 1) + (m + 1) * d * esz).sum() + per_out * m.shape[0])
 
 
+MFMA_PEAK = {"u8": 5000.0, "f32": 2500.0}  # dense int8 TOP/s, fp16 TFLOP/s
+
+
+def mfma_usage(dtype, deg, d, r_max, kernel_ms):
+    """Matrix-unit work of one sweep launch: the executed MFMA operations of
+    the batched kernel (uint8: three 32 x 32 x 32 int8 blocks per vertex and
+    32-dimension step; float32: the blocks on and above the diagonal of the
+    row blocks in use, three 32 x 32 x 16 FP16 products per 16-dimension step)
+    and the Gram's useful work (one product per candidate pair above the
+    diagonal), each over the kernel's mean time, against the dense peak."""
+    import numpy as np
+
+    m = deg.astype(np.int64)
+    if dtype == np.uint8:
+        steps = (d + 31) // 32
+        executed = int(m.shape[0]) * 3 * steps * (32 * 32 * 32 * 2)
+        key, unit = "u8", "TOP/s"
+    else:
+        nbu = np.maximum(1, np.minimum((r_max + 31) // 32, (m + 31) // 32))
+        steps = (d + 15) // 16
+        executed = int((nbu * (nbu + 1) // 2).sum()) * 3 * steps * (32 * 32 * 16 * 2)
+        key, unit = "f32", "TFLOP/s"
+    useful = int((m * (m - 1) // 2).sum()) * d * 2
+    sec = kernel_ms * 1e-3
+    peak = MFMA_PEAK[key]
+    ach = executed / sec / 1e12
+    return {"unit": unit, "executed": round(ach, 2), "peak": peak, "frac": round(ach / peak, 4),
+            "gram_useful": round(useful / sec / 1e12, 2),
+            "executed_ops_per_launch": executed}
+
+
 def batched_kernel_name(dtype, r_max, d):
     """The kernel the sweep dispatches to for this graph shape."""
     import numpy as np
@@ -527,6 +558,9 @@ def main():
                 "kernel": batched_kernel_name(w.X.dtype, spec.base_R, d),
                 "algorithmic_bytes_per_launch": abytes,
                 "kernel_ms_avg": round(avg_kernel_ms, 4)}
+    mfma = mfma_usage(w.X.dtype, deg_np, d, spec.base_R, avg_kernel_ms)
+    log(f"matrix units: {mfma['executed']} {mfma['unit']} executed "
+        f"({100 * mfma['frac']:.1f}% of peak), Gram useful {mfma['gram_useful']} {mfma['unit']}")
 
     # ---- plain kernel on the same inputs ----------------------------------
     plain = None
@@ -616,6 +650,7 @@ def main():
                    "vertices_per_workgroup": tune["waves"],
                    "outputs_per_step": len(outs)},
         "roofline": roofline,
+        "mfma": mfma,
         "distance_error": gram_err if gram_err is not None else
         ({"max_rel": 0.0, "mean_rel": 0.0, "note": "uint8: exact int32 distances"}
          if w.X.dtype == np.uint8 else None),

@@ -1,60 +1,157 @@
-// k_prune_f32.hip -- batched RP-Tuning for float32 points: split-FP16 MFMA
-// Gram tile with a rigorous rounding band and a canonical FP64 recheck.
+// k_prune_f32.hip -- batched RP-Tuning for float32 points: rows streamed
+// straight into FP16 matrix-unit registers, a proven rounding band, and a
+// canonical FP64 recheck of the pairs inside it.
 //
 // One wavefront runs RobustPrune(p, N_out(p), alpha, R) (Algorithm 1) for one
-// vertex p at every alpha of a sweep, for out-lists of at most 96 ids and any
-// d.  The candidate rows are streamed once, 32 dimensions at a time:
+// vertex p at every alpha of a sweep, reading each candidate row once, for
+// out-lists of up to 32 NB ids (NB = 2 or 3 row blocks) and any d:
 //
-//  a1  read:   the listed ids by slot (p itself and -1 padding are empty).
-//  a2  gather: per chunk, coalesced 16-byte loads of the slot rows and of x_p
-//              into an FP32 LDS tile; the next chunk's loads are in flight
-//              while the current one is used.
-//  a3  p-row:  lane j accumulates the canonical FP64 S(p, j) of its slot
-//              (t = (double)a - (double)b, fused multiply-add in ascending k)
-//              across the chunks -- the exact sort key and test operand.
-//  a5  Gram:   in the frame centred on p and scaled by 2^e (so that every
-//              |x_jk - x_pk| 2^e < 2^14; e from per-point max |x_k|), each
-//              FP32 difference v is split as hi + lo, two FP16 values, and
-//              G~ = sum hi hi' + hi lo' + lo hi' runs on
-//              v_mfma_f32_32x32x16_f16; for long rows every chunk starts a
-//              fresh accumulator that is then added to the total, which keeps
-//              the FP32 accumulation error near gamma_{3 * 32} instead of
-//              gamma_{3 d}.  S~(i, j) = (S(p, i) + S(p, j)) 2^2e - 2 G~(i, j)
-//              goes to an FP32 LDS tile in slot order.
+//  a1  read:   the t-th listed id is slot t (lane t, and lane t - 64 of the
+//              second word for t >= 64); p itself and -1 padding are empty.
+//  a2  gather: 16 dimensions per step, straight from global memory into the
+//              operand layout of the matrix instruction: for row block b
+//              (slots 32 b .. 32 b + 31) lane l holds dimensions
+//              16 s + 8 (l / 32) .. + 7 of row 32 b + l % 32, several steps in
+//              flight.  x_p sits in LDS.
+//  a3  p-row:  one lane swap (lanes 32..63 of block 0 with lanes 0..31 of
+//              block 1) gives lane t all 16 dimensions of slot t's row (block 2
+//              swaps with itself), and the lane accumulates the canonical FP64
+//              S(p, t): t = (double)a - (double)b, fused multiply-add, k
+//              ascending.
 //  a4  sort:   (S(p, j), id) ascending -- the order in which the repeated
-//              argmin of Algorithm 1 visits the candidates (a list already in
-//              that order skips the network); repeated ids are dropped.
-//  a6  test:   fl(num^2 S(i, j)) <= fl(den^2 S(p, j)), the condition on
-//              canonical values, is decided from S~ when S~ lies outside
-//              [P_j, K_j]: thresholds that carry the proven bound
+//              argmin of Algorithm 1 visits the candidates.  A list already in
+//              that order (every RobustPrune output is) is used as read;
+//              otherwise the keys are sorted and the rows are streamed a
+//              second time in rank order.  Repeated ids are dropped.
+//  a5  Gram:   in the frame centred on p and scaled by 2^e (every scaled
+//              difference below 2^14; e from the per-point max |x_k|), each
+//              FP32 difference is split as hi + lo, two FP16 values, and
+//              G~ = sum hi hi' + hi lo' + lo hi' runs on
+//              v_mfma_f32_32x32x16_f16; for long rows the accumulator restarts
+//              every 32 dimensions and the pieces are summed in FP32.
+//              S~(i, j) = (S(p, i) + S(p, j)) 2^2e - 2 G~(i, j) goes to an
+//              FP32 tile of the blocks on and above the diagonal, by rank
+//              (entries with j <= i hold +inf).
+//  a6  test:   fl(num^2 S(i, j)) <= fl(den^2 S(p, j)) is decided from S~
+//              outside [P_j, K_j], thresholds that carry the proven bound
 //              |S~ - S(i, j) 2^2e| <= c1 s + c2 sqrt(s) + c3 (s = S(p, j) 2^2e)
-//              and the FP64 rounding of both products.  Pairs inside the band
-//              are recomputed in canonical FP64 from the float32 rows.
-//  a7  greedy: per alpha a rank mask of survivors; the lowest survivor i is
-//              kept, row i of S~ is compared with each lane's thresholds;
-//              the chains of all alphas advance in lockstep.
+//              and the FP64 rounding of both products; pairs inside are
+//              recomputed in canonical FP64 from the rows.
+//  a7  greedy: per alpha a survivor mask over the ranks.  A row-minimum scan
+//              marks the rows that can prune at each alpha; survivors whose
+//              row cannot are kept in runs (one shift mask per step), each
+//              survivor whose row can prune is kept and one ballot over its
+//              tile row removes what it prunes.  A chain stops at its largest R.
 //  a8  write:  kept ranks are scattered to their positions, -1 padded.
-#include "f32_common.h"
+#include <math.h>
+
+#include "dev_common.h"
 
 namespace rp {
 
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
 namespace {
 
-constexpr int kRowF = kDC + 4;  // floats per LDS chunk row (16-byte aligned rows)
+constexpr int kDC = 32;  // dimensions per accumulator chunk of the Gram (long rows)
+constexpr int kMaxDimF32 = 4096;
 
 template <int NB>
 struct Shape {
-  static constexpr int MS = 32 * NB;                // candidate slots
-  static constexpr int ROWS = MS + 1;               // + x_p in row MS
-  static constexpr int SEG = (ROWS * 8 + 63) / 64;  // 16-byte loads per lane per chunk
-  static constexpr int NP = NB * (NB + 1) / 2;      // 32 x 32 blocks on and above the diagonal
-  static constexpr int NW = NB > 2 ? 2 : 1;         // 64-bit words of a rank mask
-  static constexpr int TILE_B = ROWS * kRowF * 4;   // chunk tile
-  static constexpr int SP = MS + 4;                 // S~ row stride (16-byte rows, conflict-free scans)
-  static constexpr int STILE_B = MS * SP * 4;       // S~ tile (overlays the chunk tile)
-  static constexpr int A_B = TILE_B > STILE_B ? TILE_B : STILE_B;
-  static constexpr int LDS_B = (A_B + MS * 4 + MS * 4 + 15) & ~15;
+  static constexpr int MS = 32 * NB;            // candidate slots
+  static constexpr int NW = NB > 2 ? 2 : 1;     // 64-bit words of a rank mask
+  static constexpr int NP = NB * (NB + 1) / 2;  // 32 x 32 blocks on and above the diagonal
+  static constexpr int TILE = 1024 * NP;        // S~ entries
 };
+
+// S~ tile: column block cb holds rows 0 .. 32 cb + 31; entry (i, j) sits at
+// cb_base(j / 32) + 32 i + j % 32.
+__host__ __device__ constexpr int cb_base(int cb) { return 512 * cb * (cb + 1); }
+// accumulator of block (bi, bj), bi <= bj
+__host__ __device__ constexpr int blk(int bi, int bj) { return bj * (bj + 1) / 2 + bi; }
+
+__host__ __device__ inline int xp_floats(int d) { return (d + 15) & ~15; }
+
+// LDS of one wavefront: S~ tile, S(p, .) 2^2e and its reciprocal by rank, x_p
+// zero padded to a multiple of 16 floats.
+template <int NB>
+inline int wave_lds_bytes(int d) {
+  return Shape<NB>::TILE * 4 + 2 * 64 * Shape<NB>::NW * 4 + xp_floats(d) * 4;
+}
+
+struct F32Args {
+  double c1, c2, c3;  // rounding band of S~ (scaled units)
+  int32_t nr;         // outputs per alpha (outputs are alpha-major)
+  // measurement mode: only the listed vertices, S~ compared with canonical FP64
+  const int32_t* nodes;
+  int64_t n_nodes;
+  GramErrorStats* stats;
+};
+
+// Next float toward -inf / +inf (finite inputs).
+__device__ __forceinline__ float next_down(float f) {
+  if (f == 0.f) return -1.401298464e-45f;
+  const int b = __float_as_int(f);
+  return __int_as_float(f > 0.f ? b - 1 : b + 1);
+}
+
+__device__ __forceinline__ float next_up(float f) {
+  if (f == 0.f) return 1.401298464e-45f;
+  const int b = __float_as_int(f);
+  return __int_as_float(f > 0.f ? b + 1 : b - 1);
+}
+
+// FP32 value <= x (round down) and >= x (round up).
+__device__ __forceinline__ float f32_down(double x) {
+  float f = (float)x;
+  if ((double)f > x) f = next_down(f);
+  return f;
+}
+
+__device__ __forceinline__ float f32_up(double x) {
+  float f = (float)x;
+  if ((double)f < x) f = next_up(f);
+  return f;
+}
+
+// Canonical FP64 squared distance of two float32 rows in global memory.
+template <bool VEC>
+__device__ __forceinline__ double canon_rows(const float* __restrict__ a,
+                                             const float* __restrict__ b, int d) {
+  double acc = 0.0;
+  int k = 0;
+  if (VEC) {
+    for (; k + 4 <= d; k += 4) {
+      const float4 x = *(const float4*)(a + k);
+      const float4 y = *(const float4*)(b + k);
+      double t = (double)x.x - (double)y.x;
+      acc = __fma_rn(t, t, acc);
+      t = (double)x.y - (double)y.y;
+      acc = __fma_rn(t, t, acc);
+      t = (double)x.z - (double)y.z;
+      acc = __fma_rn(t, t, acc);
+      t = (double)x.w - (double)y.w;
+      acc = __fma_rn(t, t, acc);
+    }
+  }
+  for (; k < d; ++k) {
+    const double t = (double)a[k] - (double)b[k];
+    acc = __fma_rn(t, t, acc);
+  }
+  return acc;
+}
+
+__device__ __forceinline__ bool key_less(uint64_t ah, uint32_t al, uint64_t bh, uint32_t bl) {
+  return ah < bh || (ah == bh && al < bl);
+}
+
+__device__ __forceinline__ int ff1_u64(uint64_t v) {
+  const uint64_t u = uniform_u64(v);
+  int i;
+  asm("s_ff1_i32_b64 %0, %1" : "=s"(i) : "s"(u));
+  return i;  // -1 for an empty mask
+}
 
 // Sort of up to 128 (hi, lo) keys held two per lane (a: ranks 0..63 after the
 // call, b: ranks 64..127): each half is sorted, b is reversed so a ++ b is
@@ -89,18 +186,279 @@ __device__ __forceinline__ void wave_sort128(uint64_t& ah, uint32_t& al, uint64_
   bitonic_step2<64, 1>(bh, bl, lane);
 }
 
+// Power-of-two scale of the frame centred on p: |x_jk - x_pk| <= bound < 2^ex,
+// e = 14 - ex, so every scaled difference is below 2^14 in magnitude.
+__device__ __forceinline__ int frame_exponent(float bound) {
+  int e = 0;
+  if (bound > 0.f) {
+    int ex;
+    frexpf(bound, &ex);
+    e = min(100, max(-100, 14 - ex));
+  }
+  return e;
+}
+
+__device__ __forceinline__ void split8(const float (&x)[8], const float4& p0, const float4& p1,
+                                       float scf, v8h& hi, v8h& lo) {
+  float u[8];
+  u[0] = (x[0] - p0.x) * scf;
+  u[1] = (x[1] - p0.y) * scf;
+  u[2] = (x[2] - p0.z) * scf;
+  u[3] = (x[3] - p0.w) * scf;
+  u[4] = (x[4] - p1.x) * scf;
+  u[5] = (x[5] - p1.y) * scf;
+  u[6] = (x[6] - p1.z) * scf;
+  u[7] = (x[7] - p1.w) * scf;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const _Float16 h = (_Float16)u[i];
+    hi[i] = h;
+    lo[i] = (_Float16)(u[i] - (float)h);
+  }
+}
+
+// C += A B^T over one 16-dimension step in three products: hi hi', hi lo', lo hi'.
+__device__ __forceinline__ void gram3(v16f& c, const v8h& ah, const v8h& al, const v8h& bh,
+                                      const v8h& bl) {
+  c = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, c, 0, 0, 0);
+}
+
+// Lanes 32..63 of a and lanes 0..31 of b trade places: afterwards `lo` holds
+// the first and `hi` the second 8 of the 16 dimensions of one row.  With a =
+// block 0 and b = block 1 that row is block 0's row l for lanes l < 32 and
+// block 1's row l - 32 for lanes l >= 32; with a = b = block 2 it is block 2's
+// row l % 32 in both halves.
+__device__ __forceinline__ void swap_halves(float a, float b, float& lo, float& hi) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  lo = __uint_as_float(r[0]);
+  hi = __uint_as_float(r[1]);
+}
+
+// acc + the canonical terms of one row's 16 dimensions of a step (xq: x_p's).
+__device__ __forceinline__ double row_step(double acc, const float (&a)[8], const float (&b)[8],
+                                           const float* __restrict__ xq) {
+  float lo[8], hi[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) swap_halves(a[e], b[e], lo[e], hi[e]);
+  const float4 q0 = *(const float4*)(xq);
+  const float4 q1 = *(const float4*)(xq + 4);
+  const float4 q2 = *(const float4*)(xq + 8);
+  const float4 q3 = *(const float4*)(xq + 12);
+  const float q[16] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
+                       q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const double t = (double)lo[e] - (double)q[e];
+    acc = __fma_rn(t, t, acc);
+  }
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const double t = (double)hi[e] - (double)q[8 + e];
+    acc = __fma_rn(t, t, acc);
+  }
+  return acc;
+}
+
+// The 8 dimensions 16 s + 8 half .. + 7 of one row block per lane.
+template <int NB>
+struct Step {
+  float x[NB][8];
+};
+
+// Every load reads valid memory: slices past d read the row's first values
+// and are zeroed before use.
+template <int NB, bool VEC>
+__device__ __forceinline__ Step<NB> fetch_step(const float* const (&rows)[NB], int d, int s,
+                                               int half) {
+  Step<NB> q;
+  const int o0 = 16 * s + 8 * half;
+  if (VEC) {
+    const int c0 = o0 < d ? o0 : 0;
+    const int c1 = o0 + 4 < d ? o0 + 4 : 0;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const float4 v0 = *(const float4*)(rows[b] + c0);
+      const float4 v1 = *(const float4*)(rows[b] + c1);
+      q.x[b][0] = v0.x;
+      q.x[b][1] = v0.y;
+      q.x[b][2] = v0.z;
+      q.x[b][3] = v0.w;
+      q.x[b][4] = v1.x;
+      q.x[b][5] = v1.y;
+      q.x[b][6] = v1.z;
+      q.x[b][7] = v1.w;
+    }
+  } else {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) q.x[b][e] = rows[b][o0 + e < d ? o0 + e : 0];
+    }
+  }
+  return q;
+}
+
+// The first PF steps of a pass, requested ahead of it (named buffers, so
+// nothing is indexed at run time).
+template <int NB>
+struct Ring {
+  Step<NB> a, b, c, d;
+};
+
+template <int NB, bool VEC, int PF>
+__device__ __forceinline__ void ring_fill(Ring<NB>& r, const float* const (&rows)[NB], int d,
+                                          int half) {
+  r.a = fetch_step<NB, VEC>(rows, d, 0, half);
+  r.b = fetch_step<NB, VEC>(rows, d, 1, half);
+  if (PF > 2) r.c = fetch_step<NB, VEC>(rows, d, 2, half);
+  if (PF > 3) r.d = fetch_step<NB, VEC>(rows, d, 3, half);
+}
+
+// One pass over this lane's rows (rows[b]: block b's row l % 32) whose first
+// PF steps are in `ring`: the Gram blocks into cur / tot and, with PROW, the
+// canonical S(p, .) of slot lane (sp[0]) and of slot 64 + l % 32 (sp[1],
+// three blocks).  nbu: blocks in use.
+template <int NB, bool CSUM, bool PROW, bool VEC, int PF>
+__device__ __forceinline__ void gram_pass(Ring<NB>& ring, const float* const (&rows)[NB], int d,
+                                          int nbu, const float* __restrict__ xq, float scf,
+                                          int half, v16f (&cur)[Shape<NB>::NP],
+                                          v16f (&tot)[Shape<NB>::NP], double (&sp)[Shape<NB>::NW]) {
+  constexpr int NP = Shape<NB>::NP;
+  const int nsteps = (d + 15) >> 4;
+  const bool ragged = (d & 15) != 0;
+  auto step = [&](const Step<NB>& q, int s) {
+    const int o0 = 16 * s + 8 * half;
+    float x[NB][8];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) x[b][e] = q.x[b][e];
+    }
+    if (ragged && s == nsteps - 1) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[b][e] = o0 + e < d ? x[b][e] : 0.f;
+      }
+    }
+    const float4 p0 = *(const float4*)(xq + o0);
+    const float4 p1 = *(const float4*)(xq + o0 + 4);
+    v8h hi[NB], lo[NB];
+    split8(x[0], p0, p1, scf, hi[0], lo[0]);
+    gram3(cur[blk(0, 0)], hi[0], lo[0], hi[0], lo[0]);
+    if (nbu > 1) {
+      split8(x[1], p0, p1, scf, hi[1], lo[1]);
+      gram3(cur[blk(0, 1)], hi[0], lo[0], hi[1], lo[1]);
+      gram3(cur[blk(1, 1)], hi[1], lo[1], hi[1], lo[1]);
+    }
+    if constexpr (NB > 2) {
+      if (nbu > 2) {
+        split8(x[2], p0, p1, scf, hi[2], lo[2]);
+        gram3(cur[blk(0, 2)], hi[0], lo[0], hi[2], lo[2]);
+        gram3(cur[blk(1, 2)], hi[1], lo[1], hi[2], lo[2]);
+        gram3(cur[blk(2, 2)], hi[2], lo[2], hi[2], lo[2]);
+      }
+    }
+    if (CSUM && ((s & 1) || s == nsteps - 1)) {  // a fresh accumulator every 32 dimensions
+#pragma unroll
+      for (int c = 0; c < NP; ++c) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          tot[c][v] += cur[c][v];
+          cur[c][v] = 0.f;
+        }
+      }
+    }
+    if (PROW) {
+      sp[0] = row_step(sp[0], x[0], x[1], xq + 16 * s);
+      if constexpr (NB > 2) {
+        if (nbu > 2) sp[1] = row_step(sp[1], x[2], x[2], xq + 16 * s);
+      }
+    }
+  };
+  // PF buffers in rotation, held as values (the slices of step s + PF are
+  // requested before step s is used)
+  Step<NB>& qa = ring.a;
+  Step<NB>& qb = ring.b;
+  Step<NB>& qc = ring.c;
+  Step<NB>& qd = ring.d;
+  for (int s = 0; s < nsteps; s += PF) {
+    {
+      const Step<NB> c = qa;
+      if (s + PF < nsteps) qa = fetch_step<NB, VEC>(rows, d, s + PF, half);
+      step(c, s);
+    }
+    if (s + 1 < nsteps) {
+      const Step<NB> c = qb;
+      if (s + 1 + PF < nsteps) qb = fetch_step<NB, VEC>(rows, d, s + 1 + PF, half);
+      step(c, s + 1);
+    }
+    if (PF > 2 && s + 2 < nsteps) {
+      const Step<NB> c = qc;
+      if (s + 2 + PF < nsteps) qc = fetch_step<NB, VEC>(rows, d, s + 2 + PF, half);
+      step(c, s + 2);
+    }
+    if (PF > 3 && s + 3 < nsteps) {
+      const Step<NB> c = qd;
+      if (s + 3 + PF < nsteps) qd = fetch_step<NB, VEC>(rows, d, s + 3 + PF, half);
+      step(c, s + 3);
+    }
+  }
+}
+
+// S~ of one 32 x 32 block (rows of block BI, columns of block BJ) into the
+// tile.  Accumulator layout: lane l holds column l % 32 of rows
+// 8 (v / 4) + 4 (l / 32) + v % 4 in register v.
+template <int BI, int BJ>
+__device__ __forceinline__ void store_block(float* St, const float* sr, const v16f& acc, int l32,
+                                            int half) {
+  const float scol = sr[32 * BJ + l32];
+  float4 nrow[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) nrow[q] = *(const float4*)(sr + 32 * BI + 8 * q + 4 * half);
+  float* base = St + cb_base(BJ) + 1024 * BI + 128 * half + l32;
+  const int below = l32 - 4 * half;  // column after row  <=>  below > 8 q + j
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int rr = 8 * (v >> 2) + (v & 3);
+    const float4 nq = nrow[v >> 2];
+    const float srow = (v & 3) == 0 ? nq.x : (v & 3) == 1 ? nq.y : (v & 3) == 2 ? nq.z : nq.w;
+    const float val = (srow + scol) - 2.f * acc[v];
+    base[32 * rr] = (BI != BJ || below > rr) ? val : __builtin_inff();
+  }
+}
+
+// Minimum over the 32 columns of block cb of tile row i of S~(i, j) / S(p, j)
+// (reciprocals by rank in invt; NaN for empty ranks, which fminf ignores).
+__device__ __forceinline__ float row_zmin(const float* St, const float* invt, int cb, int i,
+                                          float z) {
+  const float* row = St + cb_base(cb) + 32 * i;
+#pragma unroll
+  for (int c0 = 0; c0 < 32; c0 += 4) {
+    const float4 v = *(const float4*)(row + c0);
+    const float4 iv = *(const float4*)(invt + 32 * cb + c0);
+    z = fminf(z, fminf(fminf(v.x * iv.x, v.y * iv.y), fminf(v.z * iv.z, v.w * iv.w)));
+  }
+  return z;
+}
+
 // DIAG: measure instead of prune -- for the listed vertices, every candidate
 // pair's S~ is compared with the canonical FP64 S(i, j) (relative error, and
-// error over the proven band E_j), and nothing is written.
-template <int NA, int NB, bool CSUM, bool VEC, bool DIAG = false>
-__global__ __launch_bounds__(512) void prune_f32_kernel(GraphView g, SweepArgs a, F32Args fa,
-                                                        DevCounters* ctr) {
+// error over the proven band), and nothing is written.
+// Workgroups of up to 8 wavefronts for 64 candidates, 4 for 96 (whose
+// registers take a whole SIMD lane file).
+template <int NA, int NB, bool CSUM, bool VEC, int PF, bool CAP, bool DIAG>
+__global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphView g, SweepArgs a, F32Args fa,
+                                                        DevCounters* ctr, int32_t wave_lds) {
   using SH = Shape<NB>;
-  constexpr int MS = SH::MS;
   constexpr int NW = SH::NW;
   constexpr int NP = SH::NP;
-  constexpr int SP = SH::SP;
+  constexpr int SB = NW == 2 ? 7 : 6;  // slot bits of a sort key
   extern __shared__ __align__(16) uint8_t lds_all[];
+  const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
   if (DIAG) {
@@ -108,288 +466,117 @@ __global__ __launch_bounds__(512) void prune_f32_kernel(GraphView g, SweepArgs a
     p = fa.nodes[p];
   }
   if (p >= g.n) return;
-  uint8_t* lds = lds_all + (size_t)wave * SH::LDS_B;  // this wavefront's vertex
-  float* T = (float*)lds;                   // chunk tile, ROWS x kRowF
-  float* St = (float*)lds;                  // S~ tile, MS x SP, slot order (after the Gram)
-  float* sr = (float*)(lds + SH::A_B);      // S(p, slot) 2^2e in FP32
-  int32_t* idl = (int32_t*)(sr + MS);       // id by slot, -1 if empty
-
-  const int lane = threadIdx.x & 63;
+  uint8_t* lds = lds_all + (size_t)wave * wave_lds;
+  float* St = (float*)lds;          // S~ tile
+  float* sr = St + SH::TILE;        // S(p, .) 2^2e by rank (FP32)
+  float* invt = sr + 64 * NW;       // 1 / S(p, .) 2^2e by rank
+  float* xq = invt + 64 * NW;       // x_p, zero padded
   const int l32 = lane & 31;
   const int half = lane >> 5;
   const int d = g.d;
   const float* X = (const float*)g.X;
+  const int xpf = xp_floats(d);
 
-  // ---- a1 ------------------------------------------------------------------
-  const int m = g.deg[p];
-  int idw[NW];
-#pragma unroll
-  for (int w = 0; w < NW; ++w) {
-    const int s = lane + 64 * w;
-    int id = -1;
-    if (s < MS && s < m) id = g.nbr[p * g.r_max + s];
-    if (id == (int)p) id = -1;
-    idw[w] = id;
-    if (s < MS) idl[s] = id;
-  }
-
-  // power-of-two scale: |x_jk - x_pk| <= max|x_j| + max|x_p| < 2^ex, e = 14 - ex
-  float mj = 0.f;
-#pragma unroll
-  for (int w = 0; w < NW; ++w)
-    if (idw[w] >= 0) mj = fmaxf(mj, g.maxabs[idw[w]]);
-  for (int off = 32; off > 0; off >>= 1) mj = fmaxf(mj, __shfl_xor(mj, off, 64));
-  const float bound = mj + g.maxabs[p];
-  const int e = frame_exponent(bound);
-  const float scf = ldexpf(1.f, e);
-  const double sc = ldexp(1.0, e);
-  const double sc2 = sc * sc;
-  wave_sync();
-
-  // ---- a2 + a3 + a5: streamed chunks ----------------------------------------
-  const int nseg = (m + 1) * 8;   // rows 0..m-1, then x_p; 8 x 16 bytes per row
-  const int nch = (d + kDC - 1) / kDC;
-  const int nbv = (m + 31) >> 5;  // blocks holding listed slots
-  float4 buf[SH::SEG];
-  auto issue = [&](int c0) {
-#pragma unroll
-    for (int t = 0; t < SH::SEG; ++t) {
-      const int c = lane + 64 * t;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (c < nseg) {
-        const int row = c >> 3;
-        const int col = c0 + 4 * (c & 7);
-        const int rid = row < m ? idl[row] : (int)p;
-        if (rid >= 0 && col < d) {
-          const float* src = X + (int64_t)rid * d + col;
-          if (VEC) {
-            v = *(const float4*)src;
-          } else {
-            v.x = src[0];
-            if (col + 1 < d) v.y = src[1];
-            if (col + 2 < d) v.z = src[2];
-            if (col + 3 < d) v.w = src[3];
-          }
-        }
-      }
-      buf[t] = v;
-    }
-  };
-
-  double sp[NW];
-#pragma unroll
-  for (int w = 0; w < NW; ++w) sp[w] = 0.0;
-  v16f cur[NP], tot[NP];
-#pragma unroll
-  for (int q = 0; q < NP; ++q) {
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      cur[q][v] = 0.f;
-      tot[q][v] = 0.f;
-    }
-  }
-
-  issue(0);
-  for (int ch = 0; ch < nch; ++ch) {
-    const int c0 = ch * kDC;
-    const int dc = min(kDC, d - c0);
-    wave_sync();  // the previous chunk's reads are done
-#pragma unroll
-    for (int t = 0; t < SH::SEG; ++t) {
-      const int c = lane + 64 * t;
-      if (c < nseg) {
-        const int row = c >> 3;
-        const int lrow = row < m ? row : MS;
-        *(float4*)(T + lrow * kRowF + 4 * (c & 7)) = buf[t];
-      }
-    }
-    if (ch + 1 < nch) issue(c0 + kDC);
-    wave_sync();
-
-    // canonical S(p, j), k ascending
-    const float* xp = T + MS * kRowF;
+  // ---- a1: the list of vertex q (ids by slot, degree) -----------------------
+  auto load_list = [&](int64_t q, int (&raw)[NW], int& mq) {
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
       const int s = lane + 64 * w;
-      if (s < MS) {
-        const float* xj = T + s * kRowF;
-        double acc = sp[w];
-        int k = 0;
-        for (; k + 4 <= dc; k += 4) {
-          const float4 xa = *(const float4*)(xj + k);
-          const float4 xb = *(const float4*)(xp + k);
-          double t = (double)xa.x - (double)xb.x;
-          acc = __fma_rn(t, t, acc);
-          t = (double)xa.y - (double)xb.y;
-          acc = __fma_rn(t, t, acc);
-          t = (double)xa.z - (double)xb.z;
-          acc = __fma_rn(t, t, acc);
-          t = (double)xa.w - (double)xb.w;
-          acc = __fma_rn(t, t, acc);
-        }
-        for (; k < dc; ++k) {
-          const double t = (double)xj[k] - (double)xp[k];
-          acc = __fma_rn(t, t, acc);
-        }
-        sp[w] = acc;
-      }
+      raw[w] = s < g.r_max && s < SH::MS ? g.nbr[q * g.r_max + s] : -1;
     }
+    mq = g.deg[q];
+  };
+  // usable ids, this lane's rows, and the loads vertex q starts with: scale
+  // inputs, x_p, then the first steps of the rows
+  int idw[NW];
+  const float* rows[NB];
+  float mjl = 0.f, mp = 0.f;
+  float4 xv;
+  Ring<NB> ring;
+  auto prepare = [&](int64_t q, const int (&raw)[NW], int mq) {
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const int s = lane + 64 * w;
+      idw[w] = (s < mq && raw[w] != (int)q) ? raw[w] : -1;
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int id = b < 2 ? __shfl(idw[0], 32 * b + l32, 64) : __shfl(idw[NW - 1], l32, 64);
+      rows[b] = X + (int64_t)(id >= 0 ? id : (int)q) * d;
+    }
+    mjl = 0.f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w)
+      if (idw[w] >= 0) mjl = fmaxf(mjl, g.maxabs[idw[w]]);
+    mp = g.maxabs[q];
+    const float* xrow = X + q * d;
+    xv = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (VEC) {
+      if (4 * lane < d) xv = *(const float4*)(xrow + 4 * lane);
+    } else {
+      const int c = 4 * lane;
+      xv.x = c < d ? xrow[c] : 0.f;
+      xv.y = c + 1 < d ? xrow[c + 1] : 0.f;
+      xv.z = c + 2 < d ? xrow[c + 2] : 0.f;
+      xv.w = c + 3 < d ? xrow[c + 3] : 0.f;
+    }
+    ring_fill<NB, VEC, PF>(ring, rows, d, half);
+  };
 
-    // Gram on MFMA: rows of block b are slots 32 b + l32; lane half h holds
-    // dimensions 8 h .. 8 h + 7 of each 16-wide step.
+  int m, raw[NW];
+  load_list(p, raw, m);
+  prepare(p, raw, m);
+  unsigned long long rechecks = 0;
+  double dg_max_rel = 0.0, dg_sum_rel = 0.0, dg_max_band = 0.0;
+  unsigned long long dg_pairs = 0;
+  const int nbu = max(1, min(NB, (m + 31) >> 5));  // uniform: blocks holding listed slots
+
+  float mj = mjl;
+  for (int off = 32; off > 0; off >>= 1) mj = fmaxf(mj, __shfl_xor(mj, off, 64));
+  const int e = frame_exponent(mj + mp);
+  const float scf = ldexpf(1.f, e);
+  const double sc = ldexp(1.0, e);
+  const double sc2 = sc * sc;
+  if (4 * lane < xpf) *(float4*)(xq + 4 * lane) = xv;
+  for (int c = 4 * lane + 256; c < xpf; c += 256) {  // long rows
+    const float* xrow = X + p * d;
+    float4 v;
+    v.x = c < d ? xrow[c] : 0.f;
+    v.y = c + 1 < d ? xrow[c + 1] : 0.f;
+    v.z = c + 2 < d ? xrow[c + 2] : 0.f;
+    v.w = c + 3 < d ? xrow[c + 3] : 0.f;
+    *(float4*)(xq + c) = v;
+  }
+  wave_sync();
+
+  // ---- a2 + a3 + a5: one pass over the rows in slot order ----------------
+  v16f cur[NP], tot[NP];
 #pragma unroll
-    for (int kk = 0; kk < kDC; kk += 16) {
-      if (kk < dc) {
-        const float* pq = xp + kk + 8 * half;
-        const float4 p0 = *(const float4*)pq;
-        const float4 p1 = *(const float4*)(pq + 4);
-        v8h hi[NB], lo[NB];
+  for (int c = 0; c < NP; ++c) {
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          if (b >= nbv) break;  // uniform
-          const float* xr = T + (32 * b + l32) * kRowF + kk + 8 * half;
-          const float4 x0 = *(const float4*)xr;
-          const float4 x1 = *(const float4*)(xr + 4);
-          float u[8];
-          u[0] = (x0.x - p0.x) * scf;
-          u[1] = (x0.y - p0.y) * scf;
-          u[2] = (x0.z - p0.z) * scf;
-          u[3] = (x0.w - p0.w) * scf;
-          u[4] = (x1.x - p1.x) * scf;
-          u[5] = (x1.y - p1.y) * scf;
-          u[6] = (x1.z - p1.z) * scf;
-          u[7] = (x1.w - p1.w) * scf;
-#pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            const _Float16 h = (_Float16)u[i];
-            hi[b][i] = h;
-            lo[b][i] = (_Float16)(u[i] - (float)h);
-          }
-        }
-        int q = 0;
-#pragma unroll
-        for (int bi = 0; bi < NB; ++bi) {
-#pragma unroll
-          for (int bj = bi; bj < NB; ++bj, ++q) {
-            if (bj < nbv) {
-              cur[q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(hi[bi], hi[bj], cur[q], 0, 0, 0);
-              cur[q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(hi[bi], lo[bj], cur[q], 0, 0, 0);
-              cur[q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(lo[bi], hi[bj], cur[q], 0, 0, 0);
-            }
-          }
-        }
-      }
-    }
-    if (CSUM) {
-#pragma unroll
-      for (int q = 0; q < NP; ++q) {
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          tot[q][v] += cur[q][v];
-          cur[q][v] = 0.f;
-        }
-      }
+    for (int v = 0; v < 16; ++v) {
+      cur[c][v] = 0.f;
+      tot[c][v] = 0.f;
     }
   }
-
+  double sp[NW];
 #pragma unroll
-  for (int w = 0; w < NW; ++w) {
-    const int s = lane + 64 * w;
-    if (s < MS) sr[s] = (float)(sp[w] * sc2);
-  }
-  wave_sync();  // every chunk-tile read is done; sr is visible
-
-  // S~ tile in slot order (both triangles; one writer per entry).
-  // Accumulator layout of a 32 x 32 block: lane l holds column l % 32 of rows
-  // 8 (v / 4) + 4 (l / 32) + v % 4 in register v.
-  {
-    int q = 0;
-#pragma unroll
-    for (int bi = 0; bi < NB; ++bi) {
-#pragma unroll
-      for (int bj = bi; bj < NB; ++bj, ++q) {
-        if (bj < nbv) {
-          const int cs = 32 * bj + l32;
-          const float scol = sr[cs];
-#pragma unroll
-          for (int v = 0; v < 16; ++v) {
-            const int rs = 32 * bi + 8 * (v >> 2) + 4 * half + (v & 3);
-            const float gv = CSUM ? tot[q][v] : cur[q][v];
-            const float val = (sr[rs] + scol) - 2.f * gv;
-            if (bi != bj) {
-              St[rs * SP + cs] = val;
-              St[cs * SP + rs] = val;
-            } else {
-              St[rs * SP + cs] = val;
-            }
-          }
-        }
-      }
-    }
-  }
-
-  if constexpr (DIAG) {
-    wave_sync();
-    double max_rel = 0.0, sum_rel = 0.0, max_band = 0.0;
-    unsigned long long pairs = 0;
-    for (int i = 0; i < m && i < MS; ++i) {
-      const int idi = idl[i];
-      if (idi < 0) continue;  // uniform
-#pragma unroll
-      for (int w = 0; w < NW; ++w) {
-        const int j = lane + 64 * w;
-        if (j > i && j < m && j < MS && idw[w] >= 0 && idw[w] != idi) {
-          const double ex = canon_rows<VEC>(X + (int64_t)idi * d, X + (int64_t)idw[w] * d, d);
-          const double ap = (double)St[i * SP + j];
-          const double err = fabs(ap - ex * sc2);
-          if (ex > 0.0) {
-            const double rel = err / (ex * sc2);
-            max_rel = fmax(max_rel, rel);
-            sum_rel += rel;
-          }
-          const double s2 = fmax((double)sr[i], (double)sr[j]) * (1.0 + 0x1p-20);
-          const double E = fa.c1 * s2 + fa.c2 * sqrt(s2) + fa.c3;
-          max_band = fmax(max_band, err / E);
-          ++pairs;
-        }
-      }
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      max_rel = fmax(max_rel, __shfl_xor(max_rel, off, 64));
-      max_band = fmax(max_band, __shfl_xor(max_band, off, 64));
-      sum_rel += __shfl_xor(sum_rel, off, 64);
-      pairs += __shfl_xor(pairs, off, 64);
-    }
-    if (lane == 0) {
-      atomicMax((unsigned long long*)&fa.stats->max_rel,
-                (unsigned long long)__double_as_longlong(max_rel));
-      atomicMax((unsigned long long*)&fa.stats->max_band,
-                (unsigned long long)__double_as_longlong(max_band));
-      atomicAdd(&fa.stats->sum_rel, sum_rel);
-      atomicAdd(&fa.stats->pairs, pairs);
-    }
-    return;
-  }
+  for (int w = 0; w < NW; ++w) sp[w] = 0.0;
+  gram_pass<NB, CSUM, true, VEC, PF>(ring, rows, d, nbu, xq, scf, half, cur, tot, sp);
 
   // ---- a4: sort by (S(p, j), id); drop repeated ids -------------------------
-  constexpr int kSlotBits = NW == 2 ? 7 : 6;
-  uint64_t kh[2];
-  uint32_t kl[2];
-#pragma unroll
-  for (int w = 0; w < 2; ++w) {
-    kh[w] = ~0ull;
-    kl[w] = ~0u;
-  }
+  uint64_t kh[NW];
+  uint32_t kl[NW];
 #pragma unroll
   for (int w = 0; w < NW; ++w) {
+    kh[w] = ~0ull;
+    kl[w] = ~0u;
     if (idw[w] >= 0) {
       kh[w] = (uint64_t)__double_as_longlong(sp[w]);
-      kl[w] = ((uint32_t)idw[w] << kSlotBits) | (uint32_t)(lane + 64 * w);
+      kl[w] = ((uint32_t)idw[w] << SB) | (uint32_t)(lane + 64 * w);
     }
   }
-  bool sorted;  // slot order is rank order
   {
-    // a list already in (S, id) order -- every RobustPrune output is -- skips the network
     bool unsorted = false;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
@@ -400,42 +587,119 @@ __global__ __launch_bounds__(512) void prune_f32_kernel(GraphView g, SweepArgs a
     if (NW == 2) {
       const uint64_t lh = shfl_u64(kh[0], 63);
       const uint32_t ll = (uint32_t)__shfl((int)kl[0], 63, 64);
-      unsorted = unsorted || (lane == 0 && key_less(kh[1], kl[1], lh, ll));
+      unsorted = unsorted || (lane == 0 && key_less(kh[NW - 1], kl[NW - 1], lh, ll));
     }
-    sorted = __ballot(unsorted) == 0;
-    if (!sorted) {
-      if (NW == 2) wave_sort128(kh[0], kl[0], kh[1], kl[1], lane);
+    if (__ballot(unsorted) != 0) {
+      // out of rank order: sort the keys, stream the rows again by rank
+      if constexpr (NW == 2) wave_sort128(kh[0], kl[0], kh[1], kl[1], lane);
       else wave_sort2(kh[0], kl[0], lane);
+      int idk[NW];
+#pragma unroll
+      for (int w = 0; w < NW; ++w) idk[w] = kh[w] != ~0ull ? (int)(kl[w] >> SB) : -1;
+      const float* rrows[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int id = b < 2 ? __shfl(idk[0], 32 * b + l32, 64) : __shfl(idk[NW - 1], l32, 64);
+        rrows[b] = X + (int64_t)(id >= 0 ? id : (int)p) * d;
+      }
+#pragma unroll
+      for (int c = 0; c < NP; ++c) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          cur[c][v] = 0.f;
+          tot[c][v] = 0.f;
+        }
+      }
+      double unused[NW];
+      ring_fill<NB, VEC, PF>(ring, rrows, d, half);
+      gram_pass<NB, CSUM, false, VEC, PF>(ring, rrows, d, nbu, xq, scf, half, cur, tot, unused);
     }
   }
+  bool valid[NW];
   uint64_t vm[NW];
-  int slotw[NW], idr[NW];
-  double sw[NW];
-  const uint64_t last0h = shfl_u64(kh[0], 63);
-  const uint32_t last0l = (uint32_t)__shfl((int)kl[0], 63, 64);
+  int id_rank[NW];
+  double sw[NW], s2[NW];
+  {
+    const uint64_t last0h = shfl_u64(kh[0], 63);
+    const uint32_t last0l = (uint32_t)__shfl((int)kl[0], 63, 64);
 #pragma unroll
-  for (int w = 0; w < NW; ++w) {
-    // previous rank: lane - 1 of this word, or rank 63 for lane 0 of word 1
-    uint64_t ph = shfl_u64(kh[w], lane > 0 ? lane - 1 : 0);
-    uint32_t pl = (uint32_t)__shfl((int)kl[w], lane > 0 ? lane - 1 : 0, 64);
-    if (lane == 0) {
-      ph = w == 0 ? ~0ull - 1 : last0h;
-      pl = w == 0 ? 0u : last0l;
+    for (int w = 0; w < NW; ++w) {
+      // previous rank: lane - 1 of this word, or rank 63 for lane 0 of word 1
+      uint64_t ph = shfl_u64(kh[w], lane > 0 ? lane - 1 : 0);
+      uint32_t pl = (uint32_t)__shfl((int)kl[w], lane > 0 ? lane - 1 : 0, 64);
+      if (lane == 0) {
+        ph = w == 0 ? ~0ull - 1 : last0h;
+        pl = w == 0 ? 0u : last0l;
+      }
+      valid[w] = kh[w] != ~0ull && !(kh[w] == ph && (kl[w] >> SB) == (pl >> SB));
+      vm[w] = __ballot(valid[w]);
+      id_rank[w] = valid[w] ? (int)(kl[w] >> SB) : -1;
+      sw[w] = valid[w] ? __longlong_as_double((long long)kh[w]) : 0.0;
+      s2[w] = sw[w] * sc2;
+      sr[lane + 64 * w] = valid[w] ? (float)s2[w] : 0.f;
     }
-    const bool valid = kh[w] != ~0ull &&
-                       !(kh[w] == ph && (kl[w] >> kSlotBits) == (pl >> kSlotBits));
-    vm[w] = __ballot(valid);
-    slotw[w] = valid ? (int)(kl[w] & ((1u << kSlotBits) - 1)) : 0;
-    idr[w] = valid ? (int)(kl[w] >> kSlotBits) : -1;
-    sw[w] = valid ? __longlong_as_double((long long)kh[w]) : 0.0;
   }
+  wave_sync();
 
-  // ---- a6: decision thresholds of this lane's ranks -------------------------
+  // ---- a5: S~ tile by rank ----------------------------------------------------
+  auto acc_of = [&](int c) -> const v16f& { return CSUM ? tot[c] : cur[c]; };
+  store_block<0, 0>(St, sr, acc_of(blk(0, 0)), l32, half);
+  if (nbu > 1) {
+    store_block<0, 1>(St, sr, acc_of(blk(0, 1)), l32, half);
+    store_block<1, 1>(St, sr, acc_of(blk(1, 1)), l32, half);
+  }
+  if constexpr (NB > 2) {
+    if (nbu > 2) {
+      store_block<0, 2>(St, sr, acc_of(blk(0, 2)), l32, half);
+      store_block<1, 2>(St, sr, acc_of(blk(1, 2)), l32, half);
+      store_block<2, 2>(St, sr, acc_of(blk(2, 2)), l32, half);
+    }
+  }
+  // tile entry (i, rank of word w of this lane) = St[32 i + lbase[w]]; the
+  // second word's lanes 32..63 (ranks past 95, never alive) read in bounds
+  int lbase[NW];
+  lbase[0] = l32 + 1024 * half;
+  if (NW == 2) lbase[NW - 1] = cb_base(2) + l32;
+
+  if constexpr (DIAG) {
+    wave_sync();
+    double& max_rel = dg_max_rel;
+    double& sum_rel = dg_sum_rel;
+    double& max_band = dg_max_band;
+    unsigned long long& pairs = dg_pairs;
+    for (int i = 0; i < SH::MS; ++i) {
+      const uint64_t vi = i < 64 ? vm[0] : vm[NW - 1];
+      if (((vi >> (i & 63)) & 1ull) == 0) continue;  // uniform
+      const int idi = __builtin_amdgcn_readlane(i < 64 ? id_rank[0] : id_rank[NW - 1], i & 63);
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const int j = lane + 64 * w;
+        if (j > i && valid[w]) {
+          const double ex =
+              canon_rows<VEC>(X + (int64_t)idi * d, X + (int64_t)id_rank[w] * d, d);
+          const double ap = (double)St[32 * i + lbase[w]];
+          const double err = fabs(ap - ex * sc2);
+          if (ex > 0.0) {
+            const double rel = err / (ex * sc2);
+            max_rel = fmax(max_rel, rel);
+            sum_rel += rel;
+          }
+          const double sm = fmax((double)sr[i], (double)sr[j]) * (1.0 + 0x1p-20);
+          const double E = fa.c1 * sm + fa.c2 * sqrt(sm) + fa.c3;
+          max_band = fmax(max_band, err / E);
+          ++pairs;
+        }
+      }
+    }
+  } else {
+
+  // ---- a6: decision thresholds of this lane's ranks ----------------------------
   float P[NW][NA], K[NW][NA];
+  double Ew[NW];
 #pragma unroll
   for (int w = 0; w < NW; ++w) {
-    const double s2 = sw[w] * sc2;
-    const double E = fa.c1 * s2 + fa.c2 * sqrt(s2) + fa.c3;
+    const double E = fa.c1 * s2[w] + fa.c2 * sqrt(s2[w]) + fa.c3;
+    Ew[w] = E;
 #pragma unroll
     for (int ai = 0; ai < NA; ++ai) {
       // t = fl(S(p, j) fl(den^2 / num^2)) is within 2^-51.4 of den^2 S(p, j) / num^2,
@@ -447,186 +711,179 @@ __global__ __launch_bounds__(512) void prune_f32_kernel(GraphView g, SweepArgs a
     }
   }
 
-  // ---- a7: greedy, all alphas in lockstep ----------------------------------
+  // Rows that can prune: row i can remove some j > i at alpha_k only if
+  // S~(i, j) <= K_k(j), which implies fl(S~(i, j) fl(1 / s_j)) <=
+  // fl(K_k(j) fl(1 / s_j)) (the same reciprocal, monotone rounding).  The
+  // right side is at most (ratio_k (1 + 2^-48) + E_j / s_j)(1 + 2^-21): K_k(j)
+  // is t (1 + 2^-49) 2^2e + E_j rounded up, t = fl(S(p, j) ratio_k), with
+  // FP64 roundings of 2^-53 and FP32 ones of 2^-24 (K is a normal float: it
+  // exceeds c3).  So with eps >= max_j E_j / s_j,
+  // kappa_k = (ratio_k (1 + 2^-48) + eps)(1 + 2^-20) rounded up bounds every
+  // such product, and zmin_i = min_j fl(S~(i, j) fl(1 / s_j)) <= kappa_k
+  // holds for every row that can prune (one reduction serves all alphas; a
+  // looser bound only adds rows to visit).  Empty ranks have a NaN
+  // reciprocal, which fminf ignores; S(p, j) = 0 gives 0, which keeps the
+  // row visited.  A survivor whose row cannot prune is kept with nothing
+  // removed.
+  uint64_t vis[NA][NW];
+  {
+    float inv[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      inv[w] = valid[w] ? (s2[w] > 0.0 ? (float)(1.0 / s2[w]) : 0.f) : __builtin_nanf("");
+      invt[lane + 64 * w] = inv[w];
+    }
+    wave_sync();
+    float zmin[NW];
+    // rank lane: column blocks 0 (rows 0..31 only), 1 and 2; entries on and
+    // below the diagonal hold +inf
+    zmin[0] = __builtin_inff();
+    if (lane < 32) zmin[0] = row_zmin(St, invt, 0, lane, zmin[0]);
+    if (nbu > 1) zmin[0] = row_zmin(St, invt, 1, lane, zmin[0]);
+    if constexpr (NW == 2) {
+      zmin[1] = __builtin_inff();
+      if (nbu > 2) {
+        zmin[0] = row_zmin(St, invt, 2, lane, zmin[0]);
+        if (lane < 32) zmin[1] = row_zmin(St, invt, 2, 64 + lane, zmin[1]);
+      }
+    }
+    float eps = 0.f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w)
+      if (valid[w] && s2[w] > 0.0) eps = fmaxf(eps, f32_up(Ew[w] / s2[w] * (1.0 + 0x1p-50)));
+    for (int off = 32; off > 0; off >>= 1) eps = fmaxf(eps, __shfl_xor(eps, off, 64));
+#pragma unroll
+    for (int ai = 0; ai < NA; ++ai) {
+      const float kappa = f32_up((a.ratio[ai] * (1.0 + 0x1p-48) + (double)eps) * (1.0 + 0x1p-20));
+#pragma unroll
+      for (int w = 0; w < NW; ++w) vis[ai][w] = __ballot(valid[w] && zmin[w] <= kappa);
+    }
+  }
+
+  // ---- a7: greedy, all alphas ---------------------------------------------------
+  // CAP: some output bounds R below r_max, so a chain can reach its largest R
   int rmax[NA];
 #pragma unroll
   for (int ai = 0; ai < NA; ++ai) {
-    rmax[ai] = 0;
-    for (int ir = 0; ir < fa.nr; ++ir) rmax[ai] = max(rmax[ai], a.out[ai * fa.nr + ir].R);
+    rmax[ai] = 64 * NW;
+    if (CAP) {
+      rmax[ai] = 0;
+      for (int ir = 0; ir < fa.nr; ++ir) rmax[ai] = max(rmax[ai], a.out[ai * fa.nr + ir].R);
+    }
   }
   uint64_t alive[NA][NW], kept[NA][NW];
-  int cnt[NA];
 #pragma unroll
   for (int ai = 0; ai < NA; ++ai) {
-    cnt[ai] = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
       alive[ai][w] = vm[w];
       kept[ai][w] = 0;
     }
   }
-  unsigned long long rechecks = 0;
-
+  // Chain k: the survivors before the first survivor i whose row can prune
+  // at alpha_k are kept in turn (none removes anything), then i is kept and
+  // row i removes what it prunes; the chain stops at its largest R (trimmed
+  // below).
   if constexpr (NW == 1) {
-    // Rows that can prune.  For a list in rank order, row i can remove some
-    // j > i at alpha_k only if S~(i, j) <= K_k(j) for some j, which implies
-    // fl(S~(i, j) / s_j) <= kappa_k := max_j fl(K_k(j) / s_j) (FP32 products
-    // with the same reciprocal, so the implication survives rounding).  A
-    // survivor whose row cannot prune is kept with nothing removed, so the
-    // greedy below keeps whole runs of such survivors at once and only reads
-    // the rows that can prune.  Lists out of rank order visit every row.
-    uint64_t vis[NA];
-    if (sorted) {
-      const bool v0 = (vm[0] >> lane) & 1ull;
-      const double s2 = sw[0] * sc2;
-      // 1 / s_j by rank (NaN for empty ranks, whose products are then ignored)
-      const float inv = v0 ? (s2 > 0.0 ? (float)(1.0 / s2) : 0.f) : __builtin_nanf("");
-      float* invt = sr;  // S(p, .) by slot is no longer needed
-      invt[lane] = inv;
-      wave_sync();
-      float zmin = __builtin_inff();
-      const float* myrow = St + lane * SP;
-#pragma unroll 4
-      for (int j0 = 0; j0 < MS; j0 += 4) {
-        const float4 v = *(const float4*)(myrow + j0);
-        const float4 iv = *(const float4*)(invt + j0);
-        const float z0 = v.x * iv.x, z1 = v.y * iv.y, z2 = v.z * iv.z, z3 = v.w * iv.w;
-        zmin = fminf(zmin, j0 + 0 > lane ? z0 : __builtin_inff());
-        zmin = fminf(zmin, j0 + 1 > lane ? z1 : __builtin_inff());
-        zmin = fminf(zmin, j0 + 2 > lane ? z2 : __builtin_inff());
-        zmin = fminf(zmin, j0 + 3 > lane ? z3 : __builtin_inff());
-      }
-#pragma unroll
-      for (int ai = 0; ai < NA; ++ai) {
-        float q = v0 ? K[0][ai] * inv : -__builtin_inff();
-        for (int off = 32; off > 0; off >>= 1) q = fmaxf(q, __shfl_xor(q, off, 64));
-        vis[ai] = __ballot(v0 && zmin <= q);
-      }
-    } else {
-#pragma unroll
-      for (int ai = 0; ai < NA; ++ai) vis[ai] = vm[0];
-    }
-
-    // Per chain: the survivors before the first survivor i whose row can
-    // prune are kept in turn (none removes anything), then i is kept and its
-    // row decides the rest; a chain stops at its largest R (trimmed below).
-    // Alphas arrive in descending order, so chains visit ever more rows and
-    // usually finish in index order: phase s0 advances chains s0..NA-1 while
-    // chain s0 has survivors (a finished chain repeats harmless steps).
+    // Alphas arrive in descending order, so chains visit ever more rows:
+    // phase s0 advances chains s0..NA-1 while chain s0 has survivors (a
+    // finished chain repeats harmless empty steps).
 #pragma unroll
     for (int s0 = 0; s0 < NA; ++s0) {
-    while (uniform_u64(alive[s0][0]) != 0) {
-      float row[NA];
-      int istar[NA];
-#pragma unroll
-      for (int ai = s0; ai < NA; ++ai) {
-        const uint64_t al = uniform_u64(alive[ai][0]);
-        int i = ff1_u64(al & vis[ai]);
-        const uint64_t upto = i < 0 ? ~0ull : (2ull << i) - 1ull;  // ranks <= i
-        const uint64_t batch = al & upto;
-        const uint64_t k = uniform_u64(kept[ai][0]) | batch;
-        kept[ai][0] = k;
-        alive[ai][0] = (i < 0 || __popcll(k) >= rmax[ai]) ? 0ull : al & ~batch;
-        i = max(i, 0);
-        istar[ai] = i;
-        const int slot_i = __builtin_amdgcn_readlane(slotw[0], i);
-        row[ai] = St[slot_i * SP + slotw[0]];
-      }
-      uint64_t amb[NA];
-      uint64_t any_amb = 0;
-#pragma unroll
-      for (int ai = s0; ai < NA; ++ai) {
-        const uint64_t pm = __ballot(row[ai] <= P[0][ai]);
-        amb[ai] = __ballot(row[ai] <= K[0][ai]) & ~pm & alive[ai][0];
-        alive[ai][0] &= ~pm;
-        any_amb |= amb[ai];
-      }
-      if (uniform_u64(any_amb) != 0) {
+      while (uniform_u64(alive[s0][0]) != 0) {
+        float row[NA];
+        int istar[NA];
 #pragma unroll
         for (int ai = s0; ai < NA; ++ai) {
-          const uint64_t am = uniform_u64(amb[ai]);
-          if (am) {
-            const int pid = __builtin_amdgcn_readlane(idr[0], istar[ai]);
-            bool prune = false;
-            if ((am >> lane) & 1ull) {
-              const double sx =
-                  canon_rows<VEC>(X + (int64_t)pid * d, X + (int64_t)idr[0] * d, d);
-              prune = alpha_test_f64(a.num2[ai], a.den2[ai], sx, sw[0]);
+          const uint64_t al = uniform_u64(alive[ai][0]);
+          const int i = ff1_u64(al & vis[ai][0]);
+          // ranks above i; with no candidate (i = -1, shift 63) none, so
+          // every survivor is kept and the chain ends
+          const uint64_t above = 0xFFFFFFFFFFFFFFFEull << (i & 63);
+          const uint64_t k = uniform_u64(kept[ai][0]) | (al & ~above);
+          kept[ai][0] = k;
+          alive[ai][0] = (CAP && __popcll(k) >= rmax[ai]) ? 0ull : al & above;
+          istar[ai] = i & 63;
+          row[ai] = St[(i & 63) * 32 + lbase[0]];
+        }
+        uint64_t amb[NA];
+        uint64_t any_amb = 0;
+#pragma unroll
+        for (int ai = s0; ai < NA; ++ai) {
+          const uint64_t pm = __ballot(row[ai] <= P[0][ai]);
+          amb[ai] = __ballot(row[ai] <= K[0][ai]) & ~pm & alive[ai][0];
+          alive[ai][0] &= ~pm;
+          any_amb |= amb[ai];
+        }
+        if (uniform_u64(any_amb) != 0) {
+#pragma unroll
+          for (int ai = s0; ai < NA; ++ai) {
+            const uint64_t am = uniform_u64(amb[ai]);
+            if (am) {
+              const int pid = __builtin_amdgcn_readlane(id_rank[0], istar[ai]);
+              bool prune = false;
+              if ((am >> lane) & 1ull) {
+                const double sx =
+                    canon_rows<VEC>(X + (int64_t)pid * d, X + (int64_t)id_rank[0] * d, d);
+                prune = alpha_test_f64(a.num2[ai], a.den2[ai], sx, sw[0]);
+              }
+              alive[ai][0] &= ~(uint64_t)__ballot(prune);
+              rechecks += __popcll(am);
             }
-            alive[ai][0] &= ~(uint64_t)__ballot(prune);
-            rechecks += __popcll(am);
           }
         }
       }
     }
-    }
-    // a chain that reached its R keeps its first R ranks
-#pragma unroll
-    for (int ai = 0; ai < NA; ++ai) {
-      const uint64_t k = kept[ai][0];
-      if (__popcll(k) > rmax[ai]) {
-        const int before = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(k >> 32),
-                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)k, 0u));
-        kept[ai][0] = __ballot(((k >> lane) & 1ull) && before < rmax[ai]);
-      }
-    }
   } else {
-  // One lockstep step advances every chain: keep its lowest survivor i, read
-  // row i of S~ (the reads of all chains are in flight together), decide the
-  // pairs outside the band, then recheck the pairs inside it.  A finished
-  // chain takes i = rank 0, which only re-sets a bit that is already kept or
-  // that the final mask with the valid ranks removes.
+  // Two mask words: each step advances every chain that still has survivors.
   for (;;) {
+    bool live[NA];
     uint64_t any = 0;
 #pragma unroll
     for (int ai = 0; ai < NA; ++ai) {
-#pragma unroll
-      for (int w = 0; w < NW; ++w) any |= alive[ai][w];
+      uint64_t al = alive[ai][0];
+      if (NW == 2) al |= alive[ai][NW - 1];
+      al = uniform_u64(al);
+      live[ai] = al != 0;
+      any |= al;
     }
-    if (uniform_u64(any) == 0) break;
+    if (any == 0) break;
     float row[NA][NW];
     int istar[NA];
-    bool hiw[NA];  // the survivor is in word 1 (ranks 64..127)
 #pragma unroll
     for (int ai = 0; ai < NA; ++ai) {
-      int i;
-      bool w1 = false;
-      if (NW == 1) {
-        i = ff1_u64(alive[ai][0]);
-      } else {
-        const int i0 = ff1_u64(alive[ai][0]);
-        const int i1 = ff1_u64(alive[ai][NW - 1]);
-        w1 = i0 < 0 && i1 >= 0;
-        i = w1 ? i1 : i0;
+      if (!live[ai]) continue;  // uniform
+      // ranks after the chosen survivor i (none if no survivor can prune:
+      // then every survivor is kept and the chain ends; shift 63 of the
+      // constant clears it)
+      const uint64_t al0 = uniform_u64(alive[ai][0]);
+      const int i0 = ff1_u64(al0 & vis[ai][0]);
+      const uint64_t above0 = 0xFFFFFFFFFFFFFFFEull << (i0 & 63);
+      int i = i0 & 63;
+      const uint64_t k0 = uniform_u64(kept[ai][0]) | (al0 & ~above0);
+      int cnt = __popcll(k0);
+      if constexpr (NW == 2) {
+        const uint64_t al1 = uniform_u64(alive[ai][1]);
+        const int i1 = ff1_u64(al1 & vis[ai][1]);
+        const bool in0 = i0 >= 0;
+        const uint64_t above1 = in0 ? ~0ull : 0xFFFFFFFFFFFFFFFEull << (i1 & 63);
+        i = in0 ? i0 : (i1 >= 0 ? 64 + i1 : 0);
+        const uint64_t k1 = uniform_u64(kept[ai][1]) | (al1 & ~above1);
+        kept[ai][1] = k1;
+        cnt += __popcll(k1);
+        alive[ai][1] = (CAP && cnt >= rmax[ai]) ? 0ull : al1 & above1;
       }
-      const bool live = i >= 0;
-      i = max(i, 0);
-      const uint64_t bit = 1ull << i;
-      if (NW == 1) {
-        kept[ai][0] |= bit;
-        alive[ai][0] &= ~bit;
-      } else {
-        kept[ai][0] |= w1 ? 0ull : bit;
-        alive[ai][0] &= w1 ? ~0ull : ~bit;
-        kept[ai][NW - 1] |= w1 ? bit : 0ull;
-        alive[ai][NW - 1] &= w1 ? ~bit : ~0ull;
-      }
-      cnt[ai] += live ? 1 : 0;
-      if (cnt[ai] >= rmax[ai]) {  // stop right after the R-th keep
-#pragma unroll
-        for (int w = 0; w < NW; ++w) alive[ai][w] = 0;
-      }
-      const int slot_i = __builtin_amdgcn_readlane(w1 ? slotw[NW - 1] : slotw[0], i);
-      const float* srow = St + slot_i * SP;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) row[ai][w] = srow[slotw[w]];
+      kept[ai][0] = k0;
+      alive[ai][0] = (CAP && cnt >= rmax[ai]) ? 0ull : al0 & above0;
       istar[ai] = i;
-      hiw[ai] = w1;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) row[ai][w] = St[32 * i + lbase[w]];
     }
     uint64_t amb[NA][NW];
     uint64_t any_amb = 0;
 #pragma unroll
     for (int ai = 0; ai < NA; ++ai) {
+      if (!live[ai]) continue;
 #pragma unroll
       for (int w = 0; w < NW; ++w) {
         const uint64_t pm = __ballot(row[ai][w] <= P[w][ai]);
@@ -638,16 +895,17 @@ __global__ __launch_bounds__(512) void prune_f32_kernel(GraphView g, SweepArgs a
     if (uniform_u64(any_amb) != 0) {
 #pragma unroll
       for (int ai = 0; ai < NA; ++ai) {
+        if (!live[ai]) continue;
+        const int is = istar[ai];
+        const int pid = __builtin_amdgcn_readlane(is < 64 ? id_rank[0] : id_rank[NW - 1], is & 63);
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
           const uint64_t am = uniform_u64(amb[ai][w]);
           if (am) {
-            const int pid =
-                __builtin_amdgcn_readlane(hiw[ai] ? idr[NW - 1] : idr[0], istar[ai]);
             bool prune = false;
             if ((am >> lane) & 1ull) {
               const double sx =
-                  canon_rows<VEC>(X + (int64_t)pid * d, X + (int64_t)idr[w] * d, d);
+                  canon_rows<VEC>(X + (int64_t)pid * d, X + (int64_t)id_rank[w] * d, d);
               prune = alpha_test_f64(a.num2[ai], a.den2[ai], sx, sw[w]);
             }
             alive[ai][w] &= ~(uint64_t)__ballot(prune);
@@ -658,72 +916,151 @@ __global__ __launch_bounds__(512) void prune_f32_kernel(GraphView g, SweepArgs a
     }
   }
   }
+  // a chain that reached its R keeps its first R ranks
 #pragma unroll
   for (int ai = 0; ai < NA; ++ai) {
-#pragma unroll
-    for (int w = 0; w < NW; ++w) kept[ai][w] &= vm[w];
-  }
-
-  // ---- a8: write every output ------------------------------------------------
-  const uint64_t below = (1ull << lane) - 1ull;
-#pragma unroll
-  for (int ai = 0; ai < NA; ++ai) {
-    int tot_k = 0;
-    int before[NW];
+    if (!CAP) break;
+    int before_w = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
-      before[w] = tot_k;
+      const uint64_t k = kept[ai][w];
+      const int before = before_w + (int)__builtin_amdgcn_mbcnt_hi(
+                                        (uint32_t)(k >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)k, 0u));
+      before_w += __popcll(k);
+      kept[ai][w] = __ballot(((k >> lane) & 1ull) && before < rmax[ai]);
+    }
+  }
+
+  // ---- a8: write every output ---------------------------------------------------
+  auto write_out = [&](const SweepOut& out, int ai) {
+    int tot_k = 0, before_w[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      before_w[w] = tot_k;
       tot_k += __popcll(kept[ai][w]);
     }
-    for (int ir = 0; ir < fa.nr; ++ir) {
-      const SweepOut& out = a.out[ai * fa.nr + ir];
-      const int R = out.R;
-      const int cntR = tot_k < R ? tot_k : R;
-      int32_t* orow = out.nbr + p * R;
+    const int R = out.R;
+    const int cntR = tot_k < R ? tot_k : R;
+    int32_t* orow = out.nbr + p * R;
 #pragma unroll
-      for (int w = 0; w < NW; ++w) {
-        const uint64_t km = kept[ai][w];
-        const int pos = before[w] + __popcll(km & below);
-        if (((km >> lane) & 1ull) && pos < R) orow[pos] = idr[w];
-      }
-      for (int t = cntR + lane; t < R; t += 64) orow[t] = -1;
-      if (lane == 0) out.deg[p] = cntR;
+    for (int w = 0; w < NW; ++w) {
+      const uint64_t km = kept[ai][w];
+      const int pos = before_w[w] + __popcll(km & ((1ull << lane) - 1ull));
+      if (((km >> lane) & 1ull) && pos < R) orow[pos] = id_rank[w];
+    }
+    for (int t = cntR + lane; t < R; t += 64) orow[t] = -1;
+    if (lane == 0) out.deg[p] = cntR;
+  };
+  if (fa.nr == 1) {  // one bound per alpha: fixed argument offsets, loaded together
+#pragma unroll
+    for (int ai = 0; ai < NA; ++ai) write_out(a.out[ai], ai);
+  } else {
+#pragma unroll
+    for (int ai = 0; ai < NA; ++ai)
+      for (int ir = 0; ir < fa.nr; ++ir) write_out(a.out[ai * fa.nr + ir], ai);
+  }
+  }  // not DIAG
+
+
+  if constexpr (DIAG) {
+    for (int off = 32; off > 0; off >>= 1) {
+      dg_max_rel = fmax(dg_max_rel, __shfl_xor(dg_max_rel, off, 64));
+      dg_max_band = fmax(dg_max_band, __shfl_xor(dg_max_band, off, 64));
+      dg_sum_rel += __shfl_xor(dg_sum_rel, off, 64);
+      dg_pairs += __shfl_xor(dg_pairs, off, 64);
+    }
+    if (lane == 0) {
+      atomicMax((unsigned long long*)&fa.stats->max_rel,
+                (unsigned long long)__double_as_longlong(dg_max_rel));
+      atomicMax((unsigned long long*)&fa.stats->max_band,
+                (unsigned long long)__double_as_longlong(dg_max_band));
+      atomicAdd(&fa.stats->sum_rel, dg_sum_rel);
+      atomicAdd(&fa.stats->pairs, dg_pairs);
     }
   }
   if (lane == 0 && rechecks) atomicAdd(&ctr->rechecks, rechecks);
 }
 
-}  // namespace
-
-// the register-streaming kernel (k_prune_f32_reg.hip) for out-lists of at most
-// 64 ids with 16-byte row slices; this one for the other shapes
-bool prune_f32r_supported(const GraphView& g);
-int prune_f32r_wave_lds(const GraphView& g);
-hipError_t launch_prune_f32r(const GraphView& g, const SweepArgs& a, F32Args fa,
-                             DevCounters* ctr, hipStream_t s);
-hipError_t launch_gram_error_f32r(const GraphView& g, const SweepArgs& a, F32Args fa,
-                                  DevCounters* ctr, hipStream_t s);
-
-int prune_f32_wave_lds(const GraphView& g) {
-  if (prune_f32r_supported(g)) return prune_f32r_wave_lds(g);
-  return g.r_max > 64 ? Shape<3>::LDS_B : Shape<2>::LDS_B;
+// Bound of |S~ - S(i, j) 2^2e| for every rank i before j (S(p, i) <= S(p, j)),
+// s = S(p, j) 2^2e, U = (x - x_p) 2^e exact:
+//   e1 = 2^-22 + 2^-23  relative error of hi + lo against U (FP32 subtraction
+//                       2^-24, rounding of lo 2^-22);
+//   ea = 2^-14          absolute error of one element whose hi or lo is an
+//                       FP16 subnormal, even if the matrix unit flushes it;
+//   dropped lo lo'      <= 2^-22 (1 + 2^-9) s;
+//   FP32 accumulation   gamma over the additions into one accumulator, with
+//                       unit 2^-23 (covers truncating hardware), plus the
+//                       gamma of the chunk sums (unit 2^-24);
+//   |G~ - G| <= (2 e1 + e1^2 + lo lo' + acc) s + 2 ea sqrt(d) (1 + e1)(1 + acc) sqrt(s)
+//               + d ea^2 (1 + acc);
+//   S~ = (S(p,i) + S(p,j)) 2^2e - 2 G~ in FP32 adds 8 * 2^-24 s, and the
+//   canonical FP64 values differ from the exact ones by at most 12 d 2^-53 s.
+// Every coefficient is doubled; the FP64 threshold's own rounding is covered
+// by the (1 -/+ 2^-50) factors.  csum: the accumulator restarts every kDC
+// dimensions and the chunk results are summed in FP32.
+void f32_bound_constants(int d, bool csum, double* c1, double* c2, double* c3) {
+  auto gam = [](double n, double u) { return n * u / (1.0 - n * u); };
+  const double u24 = 0x1p-24;
+  const double e1 = 0x1p-22 + 0x1p-23;
+  const double ea = 0x1p-14;
+  const double nadd = csum ? 3.0 * kDC + 1.0 : 3.0 * d + 1.0;
+  const double g1 = gam(nadd, 0x1p-23);
+  const double g2 = csum ? gam((double)((d + kDC - 1) / kDC), u24) : 0.0;
+  const double acc = (g1 + g2 + g1 * g2) * (1.0 + 0x1p-9);
+  const double lolo = 0x1p-22 * (1.0 + 0x1p-9);
+  const double sd = sqrt((double)d);
+  *c1 = 2.0 * (2.0 * (2.0 * e1 + e1 * e1 + lolo + acc) + 8.0 * u24 + 12.0 * d * 0x1p-53);
+  *c2 = 2.0 * (2.0 * 2.0 * ea * sd * (1.0 + e1) * (1.0 + acc));
+  *c3 = 2.0 * (2.0 * d * ea * ea * (1.0 + acc));
 }
 
-bool prune_f32_supported(const GraphView& g) {
-  return g.dtype == RP_F32 && g.r_max <= 96 && g.n <= (1ll << 25) && g.maxabs != nullptr;
+// Launch shape per graph: NB row blocks, restarted accumulators for long rows,
+// 16-byte row slices when d % 4 == 0 and the point array is 16-byte aligned.
+struct Plan {
+  int nb;
+  bool csum, vec;
+  int wave_lds;
+};
+
+Plan plan_of(const GraphView& g) {
+  Plan pl;
+  pl.nb = g.r_max > 64 ? 3 : 2;
+  pl.csum = g.d > 128;
+  pl.vec = (g.d % 4) == 0 && (((uintptr_t)g.X) & 15) == 0;
+  pl.wave_lds = pl.nb == 3 ? wave_lds_bytes<3>(g.d) : wave_lds_bytes<2>(g.d);
+  return pl;
+}
+
+// Steps in flight: two for 64 candidates (three wavefronts per SIMD fit), four
+// for 96 (one wavefront per SIMD, so it carries the memory parallelism alone).
+template <int NB>
+constexpr int prefetch_steps() {
+  return NB == 3 ? 4 : 2;
 }
 
 template <int NB, bool CSUM, bool VEC>
-static hipError_t launch_shape(const GraphView& g, const SweepArgs& a, const F32Args& fa,
-                               DevCounters* ctr, hipStream_t s) {
+hipError_t launch_shape(const GraphView& g, const SweepArgs& a, const F32Args& fa,
+                        DevCounters* ctr, hipStream_t s, int wave_lds) {
+  constexpr int PF = prefetch_steps<NB>();
   const int waves =
-      waves_for(TuneKey{kKernelF32, g.dtype, g.d, g.r_max, a.n_alpha, a.n_out}, Shape<NB>::LDS_B);
-  const size_t shmem = (size_t)Shape<NB>::LDS_B * waves;
-  dim3 grid((unsigned)((g.n + waves - 1) / waves)), block(64 * waves);
-#define RP_LAUNCH_F32(NA_)                                                                  \
-  case NA_:                                                                                 \
-    hipLaunchKernelGGL((prune_f32_kernel<NA_, NB, CSUM, VEC>), grid, block, shmem, s, g, a, \
-                       fa, ctr);                                                            \
+      min(waves_for(TuneKey{kKernelF32, g.dtype, g.d, g.r_max, a.n_alpha, a.n_out}, wave_lds),
+          NB == 3 ? 4 : 8);  // within the launch bounds
+  const dim3 grid((unsigned)((g.n + waves - 1) / waves)), block(64 * waves);
+  const size_t shmem = (size_t)wave_lds * waves;
+  // a bound below r_max needs the chains' keep counts (always kept for the
+  // rarer shapes: 96 candidates, unaligned rows)
+  bool cap = NB == 3 || !VEC;
+  for (int o = 0; o < a.n_out; ++o) cap = cap || a.out[o].R < g.r_max;
+#define RP_LAUNCH_F32(NA_)                                                                 \
+  case NA_:                                                                                \
+    if (cap) {                                                                             \
+      auto k = prune_f32_kernel<NA_, NB, CSUM, VEC, PF, true, false>;                      \
+      hipLaunchKernelGGL(k, grid, block, shmem, s, g, a, fa, ctr, wave_lds);              \
+    } else if constexpr (NB == 2 && VEC) {                                                 \
+      auto k = prune_f32_kernel<NA_, NB, CSUM, VEC, PF, false, false>;                     \
+      hipLaunchKernelGGL(k, grid, block, shmem, s, g, a, fa, ctr, wave_lds);              \
+    }                                                                                      \
     break;
   switch (a.n_alpha) {
     RP_LAUNCH_F32(1)
@@ -742,46 +1079,89 @@ static hipError_t launch_shape(const GraphView& g, const SweepArgs& a, const F32
 }
 
 template <int NB, bool CSUM, bool VEC>
-static hipError_t launch_diag(const GraphView& g, const SweepArgs& a, const F32Args& fa,
-                              DevCounters* ctr, hipStream_t s) {
-  const size_t shmem = Shape<NB>::LDS_B;
-  hipLaunchKernelGGL((prune_f32_kernel<1, NB, CSUM, VEC, true>), dim3((unsigned)fa.n_nodes),
-                     dim3(64), shmem, s, g, a, fa, ctr);
+hipError_t launch_diag(const GraphView& g, const SweepArgs& a, const F32Args& fa,
+                       DevCounters* ctr, hipStream_t s, int wave_lds) {
+  constexpr int PF = prefetch_steps<NB>();
+  auto k = prune_f32_kernel<1, NB, CSUM, VEC, PF, false, true>;
+  hipLaunchKernelGGL(k, dim3((unsigned)fa.n_nodes), dim3(64), wave_lds, s, g, a, fa, ctr,
+                     wave_lds);
   return hipGetLastError();
 }
 
-template <bool VEC>
-static hipError_t diag_vec(const GraphView& g, const SweepArgs& a, F32Args& fa, DevCounters* ctr,
-                           hipStream_t s) {
-  if (g.r_max > 64) {
-    f32_bound_constants(g.d, true, &fa.c1, &fa.c2, &fa.c3);
-    return launch_diag<3, true, VEC>(g, a, fa, ctr, s);
+// Runs L<NB, CSUM, VEC> for the graph's plan.
+template <template <int, bool, bool> class L>
+hipError_t dispatch(const Plan& pl, const GraphView& g, const SweepArgs& a, const F32Args& fa,
+                    DevCounters* ctr, hipStream_t s) {
+  if (pl.nb == 3) {
+    if (pl.csum)
+      return pl.vec ? L<3, true, true>::run(g, a, fa, ctr, s, pl.wave_lds)
+                    : L<3, true, false>::run(g, a, fa, ctr, s, pl.wave_lds);
+    return pl.vec ? L<3, false, true>::run(g, a, fa, ctr, s, pl.wave_lds)
+                  : L<3, false, false>::run(g, a, fa, ctr, s, pl.wave_lds);
   }
-  if (g.d > 128) {
-    f32_bound_constants(g.d, true, &fa.c1, &fa.c2, &fa.c3);
-    return launch_diag<2, true, VEC>(g, a, fa, ctr, s);
-  }
-  f32_bound_constants(g.d, false, &fa.c1, &fa.c2, &fa.c3);
-  return launch_diag<2, false, VEC>(g, a, fa, ctr, s);
+  if (pl.csum)
+    return pl.vec ? L<2, true, true>::run(g, a, fa, ctr, s, pl.wave_lds)
+                  : L<2, true, false>::run(g, a, fa, ctr, s, pl.wave_lds);
+  return pl.vec ? L<2, false, true>::run(g, a, fa, ctr, s, pl.wave_lds)
+                : L<2, false, false>::run(g, a, fa, ctr, s, pl.wave_lds);
 }
 
-template <bool VEC>
-static hipError_t launch_vec(const GraphView& g, const SweepArgs& a, F32Args& fa,
-                             DevCounters* ctr, hipStream_t s) {
-  if (g.r_max > 64) {
-    f32_bound_constants(g.d, true, &fa.c1, &fa.c2, &fa.c3);
-    return launch_shape<3, true, VEC>(g, a, fa, ctr, s);
+template <int NB, bool CSUM, bool VEC>
+struct SweepLaunch {
+  static hipError_t run(const GraphView& g, const SweepArgs& a, const F32Args& fa,
+                        DevCounters* ctr, hipStream_t s, int wave_lds) {
+    return launch_shape<NB, CSUM, VEC>(g, a, fa, ctr, s, wave_lds);
   }
-  if (g.d > 128) {
-    f32_bound_constants(g.d, true, &fa.c1, &fa.c2, &fa.c3);
-    return launch_shape<2, true, VEC>(g, a, fa, ctr, s);
+};
+
+template <int NB, bool CSUM, bool VEC>
+struct DiagLaunch {
+  static hipError_t run(const GraphView& g, const SweepArgs& a, const F32Args& fa,
+                        DevCounters* ctr, hipStream_t s, int wave_lds) {
+    return launch_diag<NB, CSUM, VEC>(g, a, fa, ctr, s, wave_lds);
   }
-  f32_bound_constants(g.d, false, &fa.c1, &fa.c2, &fa.c3);
-  return launch_shape<2, false, VEC>(g, a, fa, ctr, s);
+};
+
+// Sorts the alphas of a sweep in descending order (num_a^2 den_b^2 against
+// num_b^2 den_a^2) and moves every output with its alpha (outputs are
+// alpha-major: o = alpha * nr + iR).
+SweepArgs alphas_descending(const SweepArgs& a_in, int nr) {
+  SweepArgs a = a_in;
+  int order[kMaxAlphas];
+  for (int i = 0; i < a_in.n_alpha; ++i) order[i] = i;
+  for (int i = 1; i < a_in.n_alpha; ++i) {
+    const int v = order[i];
+    int j = i - 1;
+    while (j >= 0 && (uint64_t)a_in.num2[v] * a_in.den2[order[j]] >
+                         (uint64_t)a_in.num2[order[j]] * a_in.den2[v]) {
+      order[j + 1] = order[j];
+      --j;
+    }
+    order[j + 1] = v;
+  }
+  for (int k = 0; k < a_in.n_alpha; ++k) {
+    a.num2[k] = a_in.num2[order[k]];
+    a.den2[k] = a_in.den2[order[k]];
+    a.ratio[k] = a_in.ratio[order[k]];
+    for (int ir = 0; ir < nr; ++ir) {
+      a.out[k * nr + ir] = a_in.out[order[k] * nr + ir];
+      a.out[k * nr + ir].alpha_idx = k;
+    }
+  }
+  return a;
+}
+
+}  // namespace
+
+int prune_f32_wave_lds(const GraphView& g) { return plan_of(g).wave_lds; }
+
+bool prune_f32_supported(const GraphView& g) {
+  return g.dtype == RP_F32 && g.r_max <= 96 && g.d <= kMaxDimF32 && g.n <= (1ll << 25) &&
+         g.maxabs != nullptr;
 }
 
 hipError_t launch_gram_error_f32(const GraphView& g, const int32_t* nodes, int64_t n_nodes,
-                                GramErrorStats* stats, DevCounters* ctr, hipStream_t s) {
+                                 GramErrorStats* stats, DevCounters* ctr, hipStream_t s) {
   if (n_nodes == 0) return hipSuccess;
   SweepArgs a = {};
   a.n_alpha = 1;
@@ -793,9 +1173,9 @@ hipError_t launch_gram_error_f32(const GraphView& g, const int32_t* nodes, int64
   fa.nodes = nodes;
   fa.n_nodes = n_nodes;
   fa.stats = stats;
-  if (prune_f32r_supported(g)) return launch_gram_error_f32r(g, a, fa, ctr, s);
-  const bool vec = (g.d % 4) == 0 && (((uintptr_t)g.X) & 15) == 0;
-  return vec ? diag_vec<true>(g, a, fa, ctr, s) : diag_vec<false>(g, a, fa, ctr, s);
+  const Plan pl = plan_of(g);
+  f32_bound_constants(g.d, pl.csum, &fa.c1, &fa.c2, &fa.c3);
+  return dispatch<DiagLaunch>(pl, g, a, fa, ctr, s);
 }
 
 hipError_t launch_prune_f32(const GraphView& g, const SweepArgs& a_in, DevCounters* ctr,
@@ -805,9 +1185,9 @@ hipError_t launch_prune_f32(const GraphView& g, const SweepArgs& a_in, DevCounte
   fa.nr = a_in.n_out / a_in.n_alpha;
   // the kernel takes the alphas in descending order
   const SweepArgs a = alphas_descending(a_in, fa.nr);
-  if (prune_f32r_supported(g)) return launch_prune_f32r(g, a, fa, ctr, s);
-  const bool vec = (g.d % 4) == 0 && (((uintptr_t)g.X) & 15) == 0;
-  return vec ? launch_vec<true>(g, a, fa, ctr, s) : launch_vec<false>(g, a, fa, ctr, s);
+  const Plan pl = plan_of(g);
+  f32_bound_constants(g.d, pl.csum, &fa.c1, &fa.c2, &fa.c3);
+  return dispatch<SweepLaunch>(pl, g, a, fa, ctr, s);
 }
 
 }  // namespace rp

@@ -358,21 +358,25 @@ __device__ __forceinline__ void node_back(const uint8_t* C, const SweepArgs& a, 
   }
 
   // ---- a8: write every output -------------------------------------------
-#pragma unroll
-  for (int ai = 0; ai < NA; ++ai) {
+  auto write_out = [&](const SweepOut& out, int ai) {
     const uint64_t km = kept[ai];
     const int tot = __popcll(km);
     const bool mine = (km >> lane) & 1ull;
     const int pos = __popcll(km & ((1ull << lane) - 1ull));
-    for (int ir = 0; ir < NR; ++ir) {
-      const SweepOut& out = a.out[ai * NR + ir];
-      const int R = out.R;
-      const int cntR = tot < R ? tot : R;
-      int32_t* orow = out.nbr + p * R;
-      if (mine && pos < R) orow[pos] = f.id_rank;
-      for (int t = cntR + lane; t < R; t += 64) orow[t] = -1;
-      if (lane == 0) out.deg[p] = cntR;
-    }
+    const int R = out.R;
+    const int cntR = tot < R ? tot : R;
+    int32_t* orow = out.nbr + p * R;
+    if (mine && pos < R) orow[pos] = f.id_rank;
+    for (int t = cntR + lane; t < R; t += 64) orow[t] = -1;
+    if (lane == 0) out.deg[p] = cntR;
+  };
+  if (NR == 1) {  // one bound per alpha: fixed argument offsets, loaded together
+#pragma unroll
+    for (int ai = 0; ai < NA; ++ai) write_out(a.out[ai], ai);
+  } else {
+#pragma unroll
+    for (int ai = 0; ai < NA; ++ai)
+      for (int ir = 0; ir < NR; ++ir) write_out(a.out[ai * NR + ir], ai);
   }
 }
 
