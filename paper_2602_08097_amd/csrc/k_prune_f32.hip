@@ -74,10 +74,10 @@ __host__ __device__ constexpr int blk(int bi, int bj) { return bj * (bj + 1) / 2
 __host__ __device__ inline int xp_floats(int d) { return (d + 15) & ~15; }
 
 // LDS of one wavefront: S~ tile, S(p, .) 2^2e and its reciprocal by rank, x_p
-// zero padded to a multiple of 16 floats.
+// and x_p 2^e, each zero padded to a multiple of 16 floats.
 template <int NB>
 inline int wave_lds_bytes(int d) {
-  return Shape<NB>::TILE * 4 + 2 * 64 * Shape<NB>::NW * 4 + xp_floats(d) * 4;
+  return Shape<NB>::TILE * 4 + 2 * 64 * Shape<NB>::NW * 4 + 2 * xp_floats(d) * 4;
 }
 
 struct F32Args {
@@ -198,22 +198,25 @@ __device__ __forceinline__ int frame_exponent(float bound) {
   return e;
 }
 
+// u = x 2^e - x_p 2^e in one rounding (the scaled difference; x_p 2^e comes
+// from LDS), hi = fp16(u), lo = fp16(u - hi), where u - hi is exact in FP32
+// and formed by one mixed-precision fused multiply-add.
 __device__ __forceinline__ void split8(const float (&x)[8], const float4& p0, const float4& p1,
                                        float scf, v8h& hi, v8h& lo) {
   float u[8];
-  u[0] = (x[0] - p0.x) * scf;
-  u[1] = (x[1] - p0.y) * scf;
-  u[2] = (x[2] - p0.z) * scf;
-  u[3] = (x[3] - p0.w) * scf;
-  u[4] = (x[4] - p1.x) * scf;
-  u[5] = (x[5] - p1.y) * scf;
-  u[6] = (x[6] - p1.z) * scf;
-  u[7] = (x[7] - p1.w) * scf;
+  u[0] = __builtin_fmaf(x[0], scf, -p0.x);
+  u[1] = __builtin_fmaf(x[1], scf, -p0.y);
+  u[2] = __builtin_fmaf(x[2], scf, -p0.z);
+  u[3] = __builtin_fmaf(x[3], scf, -p0.w);
+  u[4] = __builtin_fmaf(x[4], scf, -p1.x);
+  u[5] = __builtin_fmaf(x[5], scf, -p1.y);
+  u[6] = __builtin_fmaf(x[6], scf, -p1.z);
+  u[7] = __builtin_fmaf(x[7], scf, -p1.w);
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const _Float16 h = (_Float16)u[i];
     hi[i] = h;
-    lo[i] = (_Float16)(u[i] - (float)h);
+    lo[i] = (_Float16)__builtin_fmaf((float)h, -1.f, u[i]);
   }
 }
 
@@ -323,7 +326,8 @@ __device__ __forceinline__ void ring_fill(Ring<NB>& r, const float* const (&rows
 // three blocks).  nbu: blocks in use.
 template <int NB, bool CSUM, bool PROW, bool VEC, int PF>
 __device__ __forceinline__ void gram_pass(Ring<NB>& ring, const float* const (&rows)[NB], int d,
-                                          int nbu, const float* __restrict__ xq, float scf,
+                                          int nbu, const float* __restrict__ xq,
+                                          const float* __restrict__ xs, float scf,
                                           int half, v16f (&cur)[Shape<NB>::NP],
                                           v16f (&tot)[Shape<NB>::NP], double (&sp)[Shape<NB>::NW]) {
   constexpr int NP = Shape<NB>::NP;
@@ -344,8 +348,8 @@ __device__ __forceinline__ void gram_pass(Ring<NB>& ring, const float* const (&r
         for (int e = 0; e < 8; ++e) x[b][e] = o0 + e < d ? x[b][e] : 0.f;
       }
     }
-    const float4 p0 = *(const float4*)(xq + o0);
-    const float4 p1 = *(const float4*)(xq + o0 + 4);
+    const float4 p0 = *(const float4*)(xs + o0);
+    const float4 p1 = *(const float4*)(xs + o0 + 4);
     v8h hi[NB], lo[NB];
     split8(x[0], p0, p1, scf, hi[0], lo[0]);
     gram3(cur[blk(0, 0)], hi[0], lo[0], hi[0], lo[0]);
@@ -471,6 +475,7 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
   float* sr = St + SH::TILE;        // S(p, .) 2^2e by rank (FP32)
   float* invt = sr + 64 * NW;       // 1 / S(p, .) 2^2e by rank
   float* xq = invt + 64 * NW;       // x_p, zero padded
+  float* xs = xq + xp_floats(g.d);  // x_p 2^e, zero padded
   const int l32 = lane & 31;
   const int half = lane >> 5;
   const int d = g.d;
@@ -537,7 +542,13 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
   const float scf = ldexpf(1.f, e);
   const double sc = ldexp(1.0, e);
   const double sc2 = sc * sc;
-  if (4 * lane < xpf) *(float4*)(xq + 4 * lane) = xv;
+  // x_p and x_p 2^e (a power-of-two scale: exact unless it leaves the
+  // normal range, where the error stays far below the subnormal term)
+  auto stage = [&](int c, float4 v) {
+    *(float4*)(xq + c) = v;
+    *(float4*)(xs + c) = make_float4(v.x * scf, v.y * scf, v.z * scf, v.w * scf);
+  };
+  if (4 * lane < xpf) stage(4 * lane, xv);
   for (int c = 4 * lane + 256; c < xpf; c += 256) {  // long rows
     const float* xrow = X + p * d;
     float4 v;
@@ -545,7 +556,7 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
     v.y = c + 1 < d ? xrow[c + 1] : 0.f;
     v.z = c + 2 < d ? xrow[c + 2] : 0.f;
     v.w = c + 3 < d ? xrow[c + 3] : 0.f;
-    *(float4*)(xq + c) = v;
+    stage(c, v);
   }
   wave_sync();
 
@@ -562,7 +573,7 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
   double sp[NW];
 #pragma unroll
   for (int w = 0; w < NW; ++w) sp[w] = 0.0;
-  gram_pass<NB, CSUM, true, VEC, PF>(ring, rows, d, nbu, xq, scf, half, cur, tot, sp);
+  gram_pass<NB, CSUM, true, VEC, PF>(ring, rows, d, nbu, xq, xs, scf, half, cur, tot, sp);
 
   // ---- a4: sort by (S(p, j), id); drop repeated ids -------------------------
   uint64_t kh[NW];
@@ -612,7 +623,8 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
       }
       double unused[NW];
       ring_fill<NB, VEC, PF>(ring, rrows, d, half);
-      gram_pass<NB, CSUM, false, VEC, PF>(ring, rrows, d, nbu, xq, scf, half, cur, tot, unused);
+      gram_pass<NB, CSUM, false, VEC, PF>(ring, rrows, d, nbu, xq, xs, scf, half, cur, tot,
+                                         unused);
     }
   }
   bool valid[NW];
@@ -984,8 +996,9 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
 
 // Bound of |S~ - S(i, j) 2^2e| for every rank i before j (S(p, i) <= S(p, j)),
 // s = S(p, j) 2^2e, U = (x - x_p) 2^e exact:
-//   e1 = 2^-22 + 2^-23  relative error of hi + lo against U (FP32 subtraction
-//                       2^-24, rounding of lo 2^-22);
+//   e1 = 2^-22 + 2^-23  relative error of hi + lo against U (the one FP32
+//                       rounding of the scaled difference 2^-24, rounding of
+//                       lo 2^-22);
 //   ea = 2^-14          absolute error of one element whose hi or lo is an
 //                       FP16 subnormal, even if the matrix unit flushes it;
 //   dropped lo lo'      <= 2^-22 (1 + 2^-9) s;
