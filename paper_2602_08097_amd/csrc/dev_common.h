@@ -175,6 +175,18 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Power-of-two scale of a float32 vertex frame: |x_jk - x_pk| <= bound <
+// 2^ex, e = 14 - ex, so every scaled difference is below 2^14 in magnitude.
+__device__ __forceinline__ int frame_exponent(float bound) {
+  int e = 0;
+  if (bound > 0.f) {
+    int ex;
+    frexpf(bound, &ex);
+    e = min(100, max(-100, 14 - ex));
+  }
+  return e;
+}
+
 // A wave-uniform 64-bit value pinned to scalar registers.
 __device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);

@@ -186,18 +186,6 @@ __device__ __forceinline__ void wave_sort128(uint64_t& ah, uint32_t& al, uint64_
   bitonic_step2<64, 1>(bh, bl, lane);
 }
 
-// Power-of-two scale of the frame centred on p: |x_jk - x_pk| <= bound < 2^ex,
-// e = 14 - ex, so every scaled difference is below 2^14 in magnitude.
-__device__ __forceinline__ int frame_exponent(float bound) {
-  int e = 0;
-  if (bound > 0.f) {
-    int ex;
-    frexpf(bound, &ex);
-    e = min(100, max(-100, 14 - ex));
-  }
-  return e;
-}
-
 // u = x 2^e - x_p 2^e in one rounding (the scaled difference; x_p 2^e comes
 // from LDS), hi = fp16(u), lo = fp16(u - hi), where u - hi is exact in FP32
 // and formed by one mixed-precision fused multiply-add.
@@ -496,6 +484,7 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
   int idw[NW];
   const float* rows[NB];
   float mjl = 0.f, mp = 0.f;
+  int fe = 0;
   float4 xv;
   Ring<NB> ring;
   auto prepare = [&](int64_t q, const int (&raw)[NW], int mq) {
@@ -510,10 +499,14 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
       rows[b] = X + (int64_t)(id >= 0 ? id : (int)q) * d;
     }
     mjl = 0.f;
+    if (g.frame_e != nullptr) {  // uniform: the graph holds the frame exponents
+      fe = g.frame_e[q];
+    } else {
 #pragma unroll
-    for (int w = 0; w < NW; ++w)
-      if (idw[w] >= 0) mjl = fmaxf(mjl, g.maxabs[idw[w]]);
-    mp = g.maxabs[q];
+      for (int w = 0; w < NW; ++w)
+        if (idw[w] >= 0) mjl = fmaxf(mjl, g.maxabs[idw[w]]);
+      mp = g.maxabs[q];
+    }
     const float* xrow = X + q * d;
     xv = make_float4(0.f, 0.f, 0.f, 0.f);
     if (VEC) {
@@ -536,9 +529,12 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
   unsigned long long dg_pairs = 0;
   const int nbu = max(1, min(NB, (m + 31) >> 5));  // uniform: blocks holding listed slots
 
-  float mj = mjl;
-  for (int off = 32; off > 0; off >>= 1) mj = fmaxf(mj, __shfl_xor(mj, off, 64));
-  const int e = frame_exponent(mj + mp);
+  int e = fe;
+  if (g.frame_e == nullptr) {
+    float mj = mjl;
+    for (int off = 32; off > 0; off >>= 1) mj = fmaxf(mj, __shfl_xor(mj, off, 64));
+    e = frame_exponent(mj + mp);
+  }
   const float scf = ldexpf(1.f, e);
   const double sc = ldexp(1.0, e);
   const double sc2 = sc * sc;

@@ -62,6 +62,29 @@ hipError_t launch_maxabs_f32(const GraphView& g, float* maxabs, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Frame exponent of every vertex: from the max |x_k| of its listed ids (p
+// itself and -1 excluded) plus its own, one wavefront per vertex.
+__global__ void frame_exponents_f32_kernel(GraphView g, int8_t* __restrict__ e) {
+  const int lane = threadIdx.x & 63;
+  const int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (p >= g.n) return;
+  const int m = g.deg[p];
+  float mj = 0.f;
+  for (int s = lane; s < m; s += 64) {
+    const int id = g.nbr[p * g.r_max + s];
+    if (id >= 0 && id != (int)p) mj = fmaxf(mj, g.maxabs[id]);
+  }
+  for (int off = 32; off > 0; off >>= 1) mj = fmaxf(mj, __shfl_xor(mj, off, 64));
+  if (lane == 0) e[p] = (int8_t)frame_exponent(mj + g.maxabs[p]);
+}
+
+hipError_t launch_frame_exponents_f32(const GraphView& g, int8_t* e, hipStream_t s) {
+  const int block = 256;
+  const int64_t grid = (g.n + 3) / 4;
+  hipLaunchKernelGGL(frame_exponents_f32_kernel, dim3((unsigned)grid), dim3(block), 0, s, g, e);
+  return hipGetLastError();
+}
+
 hipError_t launch_validate(const GraphView& g, DevCounters* ctr, hipStream_t s) {
   const int block = 256;
   const int64_t grid = (g.n + block - 1) / block;

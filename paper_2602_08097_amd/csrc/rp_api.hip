@@ -98,6 +98,23 @@ rp_status validate_adjacency(const rp::GraphView& v, rp::DevCounters* ctr, hipSt
   return RP_OK;
 }
 
+// Float32 graphs that the batched prune serves (lists of at most 96 ids) get
+// the frame exponent of every vertex once, so a sweep reads one byte per
+// vertex instead of max|x| of every candidate.
+rp_status add_frame_exponents(rp_graph* g, hipStream_t stream) {
+  g->frame_e = nullptr;
+  if (g->view.dtype != RP_F32 || !rp::prune_f32_supported(g->view)) return RP_OK;
+  if (hipMalloc(&g->frame_e, (size_t)g->view.n) != hipSuccess) {
+    (void)hipGetLastError();
+    g->frame_e = nullptr;
+    return fail(RP_ENOMEM, "hipMalloc of the frame exponents failed");
+  }
+  rp_status st = check_launch(
+      rp::launch_frame_exponents_f32(g->view, (int8_t*)g->frame_e, stream), "frame exponents");
+  if (st == RP_OK) g->view.frame_e = (const int8_t*)g->frame_e;
+  return st;
+}
+
 rp_status check_outputs(const rp_graph* g, int32_t R, const int32_t* out_nbr,
                         const int32_t* out_deg) {
   if (R < 1) return fail(RP_EINVAL, "R must be >= 1 (got %d)", R);
@@ -133,7 +150,7 @@ rp_status rp_load_graph(const void* points, int32_t dtype, int64_t n, int32_t d,
     return fail(RP_EINVAL, "points is not a device array of n*d elements");
   rp_graph* g = new (std::nothrow) rp_graph();
   if (!g) return fail(RP_ENOMEM, "host allocation failed");
-  g->view = {points, dtype, n, d, nbr, deg, r_max, start, nullptr, nullptr};
+  g->view = {points, dtype, n, d, nbr, deg, r_max, start, nullptr, nullptr, nullptr};
   g->base = nullptr;
   g->aux = nullptr;
   if (hipGetDevice(&g->device) != hipSuccess) {
@@ -159,9 +176,11 @@ rp_status rp_load_graph(const void* points, int32_t dtype, int64_t n, int32_t d,
       g->view.maxabs = (const float*)g->aux;
       st = check_launch(rp::launch_maxabs_f32(g->view, (float*)g->aux, (hipStream_t)stream),
                         "maxabs");
+      if (st == RP_OK) st = add_frame_exponents(g, (hipStream_t)stream);
     }
   }
   if (st != RP_OK) {
+    if (g->frame_e) (void)hipFree(g->frame_e);
     if (g->aux) (void)hipFree(g->aux);
     (void)hipFree(g->ctr);
     delete g;
@@ -192,8 +211,12 @@ rp_status rp_graph_derive(rp_graph_t base, const int32_t* nbr, const int32_t* de
     delete g;
     return fail(RP_ENOMEM, "hipMalloc of counters failed");
   }
+  g->view.frame_e = nullptr;
+  g->frame_e = nullptr;
   rp_status st = validate_adjacency(g->view, g->ctr, (hipStream_t)stream);
+  if (st == RP_OK) st = add_frame_exponents(g, (hipStream_t)stream);
   if (st != RP_OK) {
+    if (g->frame_e) (void)hipFree(g->frame_e);
     (void)hipFree(g->ctr);
     delete g;
     return st;
@@ -488,6 +511,7 @@ void rp_free_graph(rp_graph_t g) {
   (void)hipDeviceSynchronize();
   (void)hipFree(g->ctr);
   if (g->aux) (void)hipFree(g->aux);
+  if (g->frame_e) (void)hipFree(g->frame_e);
   delete g;
 }
 

@@ -50,6 +50,9 @@ struct GraphView {
   int32_t start;
   const uint32_t* norms;  // |x|^2 per point (uint8 points; library-owned), else null
   const float* maxabs;    // max_k |x_k| per point (float32 points; library-owned), else null
+  // per vertex, the power-of-two scale exponent of the vertex's frame for the
+  // float32 prune (from its own list and max|x|; library-owned), else null
+  const int8_t* frame_e;
 };
 
 // Measured error of the float32 kernel's approximate distances (device).
@@ -73,6 +76,7 @@ struct SearchJob {
 hipError_t launch_validate(const GraphView& g, DevCounters* ctr, hipStream_t s);
 hipError_t launch_norms_u8(const GraphView& g, uint32_t* norms, hipStream_t s);
 hipError_t launch_maxabs_f32(const GraphView& g, float* maxabs, hipStream_t s);
+hipError_t launch_frame_exponents_f32(const GraphView& g, int8_t* e, hipStream_t s);
 hipError_t launch_prune_plain(const GraphView& g, uint32_t num2, uint32_t den2, int32_t R,
                               int32_t* out_nbr, int32_t* out_deg, DevCounters* ctr,
                               hipStream_t s);
@@ -138,4 +142,5 @@ struct rp_graph {
   int64_t nodes;   // vertex-prunes enqueued, counted on the host
   void* aux;       // per-point array owned by a base handle, shared by derived ones:
                    // |x|^2 (uint8 points) or max_k |x_k| (float32 points)
+  void* frame_e;   // per-vertex frame exponents of this handle's lists (float32), or null
 };

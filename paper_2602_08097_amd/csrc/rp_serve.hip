@@ -174,6 +174,7 @@ bool admit(rp_server* s, Graph* g) {
   g->view.nbr = g->nbr;
   g->view.deg = g->deg;
   g->view.r_max = g->R;
+  g->view.frame_e = nullptr;  // the base's exponents belong to the base lists
   s->stats.resident_graphs++;
   s->stats.resident_bytes += (int64_t)bytes;
   return true;
