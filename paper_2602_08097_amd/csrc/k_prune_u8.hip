@@ -108,9 +108,7 @@ __device__ __forceinline__ int sdot16(v4i a, v4i b, int acc) {
 template <int NA, int BI, int BJ>
 __device__ __forceinline__ void decide_block(uint8_t* C, const int32_t* mnr, const v16i& acc,
                                              const int32_t (&T)[NA], int l32, int half) {
-  // S(i, j) <= T_k(j)  <=>  y = 2 G(i, j) - |u_i|^2 >= U_k = |u_j|^2 - T_k(j);
-  // |y|, |U_k| < 2^26, so y - U_k does not overflow and its sign bit is
-  // [y < U_k]
+  // S(i, j) <= T_k(j)  <=>  y = 2 G(i, j) - |u_i|^2 >= U_k = |u_j|^2 - T_k(j)
   const int32_t ncol = -mnr[32 * BJ + l32];
   int32_t U[NA];
 #pragma unroll
@@ -128,10 +126,13 @@ __device__ __forceinline__ void decide_block(uint8_t* C, const int32_t* mnr, con
     const int4 nq = nrow[v >> 2];
     const int32_t mn = (v & 3) == 0 ? nq.x : (v & 3) == 1 ? nq.y : (v & 3) == 2 ? nq.z : nq.w;
     const int32_t y = 2 * acc[v] + mn;
-    uint32_t over = 0;  // sign bits of y - U_k, no carry flags (no hazard stalls)
+    // U_k ascends with k, so the alphas that prune are 0..c-1 and the code
+    // 2^c - 1 is the last 2^(k+1) - 1 with y >= U_k (a compare and a select per
+    // alpha)
+    uint32_t t = 0;
 #pragma unroll
-    for (int k = 0; k < NA; ++k) over += (uint32_t)(y - U[k]) >> 31;
-    const uint32_t t = (BI != BJ || below > rr) ? (1u << (NA - over)) - 1u : 0u;
+    for (int k = 0; k < NA; ++k) t = y >= U[k] ? (2u << k) - 1u : t;
+    if (BI == BJ) t = below > rr ? t : 0u;
     base[32 * rr] = (uint8_t)t;
   }
 }
