@@ -451,7 +451,7 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
   constexpr int SB = NW == 2 ? 7 : 6;  // slot bits of a sort key
   extern __shared__ __align__(16) uint8_t lds_all[];
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar vertex index
   int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
   if (DIAG) {
     if (p >= fa.n_nodes) return;

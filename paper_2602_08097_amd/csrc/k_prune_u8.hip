@@ -388,7 +388,7 @@ __global__ __launch_bounds__(512) void prune_u8_kernel(GraphView g, SweepArgs a,
                                                        int32_t nr_out, int32_t wave_lds) {
   extern __shared__ __align__(16) uint8_t lds_all[];
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar vertex index
   const int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
   if (p >= g.n) return;
   uint8_t* lds = lds_all + (size_t)wave * wave_lds;
