@@ -499,14 +499,17 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
       rows[b] = X + (int64_t)(id >= 0 ? id : (int)q) * d;
     }
     mjl = 0.f;
-    if (g.frame_e != nullptr) {  // uniform: the graph holds the frame exponents
-      fe = g.frame_e[q];
-    } else {
+    if (g.frame_e == nullptr) {  // uniform: no frame exponents with the graph
 #pragma unroll
       for (int w = 0; w < NW; ++w)
         if (idw[w] >= 0) mjl = fmaxf(mjl, g.maxabs[idw[w]]);
       mp = g.maxabs[q];
     }
+    ring_fill<NB, VEC, PF>(ring, rows, d, half);
+  };
+  // loads that do not wait for the list: x_p and the frame exponent
+  auto early = [&](int64_t q) {
+    if (g.frame_e != nullptr) fe = g.frame_e[q];
     const float* xrow = X + q * d;
     xv = make_float4(0.f, 0.f, 0.f, 0.f);
     if (VEC) {
@@ -518,11 +521,11 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
       xv.z = c + 2 < d ? xrow[c + 2] : 0.f;
       xv.w = c + 3 < d ? xrow[c + 3] : 0.f;
     }
-    ring_fill<NB, VEC, PF>(ring, rows, d, half);
   };
 
   int m, raw[NW];
   load_list(p, raw, m);
+  early(p);
   prepare(p, raw, m);
   unsigned long long rechecks = 0;
   double dg_max_rel = 0.0, dg_sum_rel = 0.0, dg_max_band = 0.0;
