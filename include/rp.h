@@ -83,7 +83,10 @@ typedef struct {
  * valid and unmodified.  The adjacency is validated on the device; this call
  * synchronises `stream` and returns RP_ERANGE if any degree is outside
  * [0, r_max] or any listed id outside [0, n).  On success *out receives a new
- * handle.
+ * handle.  The handle owns one device array per point (|x|^2 for uint8 points,
+ * max_k |x_k| for float32 ones) and, for float32 graphs with r_max <= 96, one
+ * byte per vertex: the scale exponent of the vertex's frame, computed from
+ * its list here so that sweeps need not read it per candidate.
  */
 rp_status rp_load_graph(const void* points, int32_t dtype, int64_t n, int32_t d,
                         const int32_t* nbr, const int32_t* deg, int32_t r_max,
@@ -93,7 +96,8 @@ rp_status rp_load_graph(const void* points, int32_t dtype, int64_t n, int32_t d,
  * rp_graph_derive -- a handle on another graph over the same points (for
  * example a pruned graph, to search it).  Shares base's points and start
  * vertex; borrows nbr/deg like rp_load_graph and validates them the same way
- * (synchronous).  base must outlive the derived handle.
+ * (synchronous), and computes its own per-vertex frame exponents for float32
+ * graphs with r_max <= 96 (n bytes).  base must outlive the derived handle.
  */
 rp_status rp_graph_derive(rp_graph_t base, const int32_t* nbr, const int32_t* deg,
                           int32_t r_max, void* stream, rp_graph_t* out);
