@@ -45,6 +45,8 @@
 //  a8  write:  kept ranks are scattered to their positions, -1 padded.
 #include <math.h>
 
+#include <cmath>
+
 #include "dev_common.h"
 
 namespace rp {
@@ -73,11 +75,17 @@ __host__ __device__ constexpr int blk(int bi, int bj) { return bj * (bj + 1) / 2
 
 __host__ __device__ inline int xp_floats(int d) { return (d + 15) & ~15; }
 
-// LDS of one wavefront: S~ tile, S(p, .) 2^2e and its reciprocal by rank, x_p
-// and x_p 2^e, each zero padded to a multiple of 16 floats.
+// LDS of one wavefront: the S~ tile; x_p as FP64 (the canonical p-row's
+// operand); and one FP32 region that holds x_p 2^e while the rows stream,
+// then S(p, .) 2^2e by rank until the tile is written, then 1 / S(p, .) 2^2e
+// by rank.  x_p arrays are zero padded to a multiple of 16 values.
+__host__ __device__ inline int aux_floats(int d, int nw) {
+  return xp_floats(d) > 64 * nw ? xp_floats(d) : 64 * nw;
+}
+
 template <int NB>
 inline int wave_lds_bytes(int d) {
-  return Shape<NB>::TILE * 4 + 2 * 64 * Shape<NB>::NW * 4 + 2 * xp_floats(d) * 4;
+  return Shape<NB>::TILE * 4 + xp_floats(d) * 8 + aux_floats(d, Shape<NB>::NW) * 4;
 }
 
 struct F32Args {
@@ -89,26 +97,14 @@ struct F32Args {
   GramErrorStats* stats;
 };
 
-// Next float toward -inf / +inf (finite inputs).
-__device__ __forceinline__ float next_down(float f) {
-  if (f == 0.f) return -1.401298464e-45f;
-  const int b = __float_as_int(f);
-  return __int_as_float(f > 0.f ? b - 1 : b + 1);
-}
-
+// Next float toward +inf (finite inputs).
 __device__ __forceinline__ float next_up(float f) {
   if (f == 0.f) return 1.401298464e-45f;
   const int b = __float_as_int(f);
   return __int_as_float(f > 0.f ? b + 1 : b - 1);
 }
 
-// FP32 value <= x (round down) and >= x (round up).
-__device__ __forceinline__ float f32_down(double x) {
-  float f = (float)x;
-  if ((double)f > x) f = next_down(f);
-  return f;
-}
-
+// FP32 value >= x (round up).
 __device__ __forceinline__ float f32_up(double x) {
   float f = (float)x;
   if ((double)f < x) f = next_up(f);
@@ -228,26 +224,27 @@ __device__ __forceinline__ void swap_halves(float a, float b, float& lo, float& 
   hi = __uint_as_float(r[1]);
 }
 
-// acc + the canonical terms of one row's 16 dimensions of a step (xq: x_p's).
+// acc + the canonical terms of one row's 16 dimensions of a step (xq: x_p's,
+// already FP64).
 __device__ __forceinline__ double row_step(double acc, const float (&a)[8], const float (&b)[8],
-                                           const float* __restrict__ xq) {
+                                           const double* __restrict__ xq) {
   float lo[8], hi[8];
 #pragma unroll
   for (int e = 0; e < 8; ++e) swap_halves(a[e], b[e], lo[e], hi[e]);
-  const float4 q0 = *(const float4*)(xq);
-  const float4 q1 = *(const float4*)(xq + 4);
-  const float4 q2 = *(const float4*)(xq + 8);
-  const float4 q3 = *(const float4*)(xq + 12);
-  const float q[16] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
-                       q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const double t = (double)lo[e] - (double)q[e];
+  for (int e = 0; e < 8; e += 2) {
+    const double2 q = *(const double2*)(xq + e);
+    double t = (double)lo[e] - q.x;
+    acc = __fma_rn(t, t, acc);
+    t = (double)lo[e + 1] - q.y;
     acc = __fma_rn(t, t, acc);
   }
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const double t = (double)hi[e] - (double)q[8 + e];
+  for (int e = 0; e < 8; e += 2) {
+    const double2 q = *(const double2*)(xq + 8 + e);
+    double t = (double)hi[e] - q.x;
+    acc = __fma_rn(t, t, acc);
+    t = (double)hi[e + 1] - q.y;
     acc = __fma_rn(t, t, acc);
   }
   return acc;
@@ -314,7 +311,7 @@ __device__ __forceinline__ void ring_fill(Ring<NB>& r, const float* const (&rows
 // three blocks).  nbu: blocks in use.
 template <int NB, bool CSUM, bool PROW, bool VEC, int PF>
 __device__ __forceinline__ void gram_pass(Ring<NB>& ring, const float* const (&rows)[NB], int d,
-                                          int nbu, const float* __restrict__ xq,
+                                          int nbu, const double* __restrict__ xq,
                                           const float* __restrict__ xs, float scf,
                                           int half, v16f (&cur)[Shape<NB>::NP],
                                           v16f (&tot)[Shape<NB>::NP], double (&sp)[Shape<NB>::NW]) {
@@ -460,10 +457,10 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
   if (p >= g.n) return;
   uint8_t* lds = lds_all + (size_t)wave * wave_lds;
   float* St = (float*)lds;          // S~ tile
-  float* sr = St + SH::TILE;        // S(p, .) 2^2e by rank (FP32)
-  float* invt = sr + 64 * NW;       // 1 / S(p, .) 2^2e by rank
-  float* xq = invt + 64 * NW;       // x_p, zero padded
-  float* xs = xq + xp_floats(g.d);  // x_p 2^e, zero padded
+  double* xq = (double*)(St + SH::TILE);  // x_p in FP64, zero padded
+  float* xs = (float*)(xq + xp_floats(g.d));  // x_p 2^e while the rows stream,
+  float* sr = xs;                              // then S(p, .) 2^2e by rank,
+  float* invt = xs;                            // then its reciprocal
   const int l32 = lane & 31;
   const int half = lane >> 5;
   const int d = g.d;
@@ -544,7 +541,8 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
   // x_p and x_p 2^e (a power-of-two scale: exact unless it leaves the
   // normal range, where the error stays far below the subnormal term)
   auto stage = [&](int c, float4 v) {
-    *(float4*)(xq + c) = v;
+    *(double2*)(xq + c) = make_double2((double)v.x, (double)v.y);
+    *(double2*)(xq + c + 2) = make_double2((double)v.z, (double)v.w);
     *(float4*)(xs + c) = make_float4(v.x * scf, v.y * scf, v.z * scf, v.w * scf);
   };
   if (4 * lane < xpf) stage(4 * lane, xv);
@@ -626,6 +624,7 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
                                          unused);
     }
   }
+  wave_sync();  // the x_p 2^e reads are done before the region takes S(p, .)
   bool valid[NW];
   uint64_t vm[NW];
   int id_rank[NW];
@@ -705,31 +704,41 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
   } else {
 
   // ---- a6: decision thresholds of this lane's ranks ----------------------------
+  // P and K in FP32 from one fused multiply-add each.  With s = S(p, j) 2^2e
+  // (exact), ts = fl32(s), rd <= ratio (1 - 2^-22) and ru >= ratio (1 + 2^-22)
+  // for the exact ratio den^2 / num^2 (host-rounded floats), and
+  // eu >= E (1 + 2^-22):
+  //   P = fl(ts rd - eu) <= s ratio (1 - 2^-23) - E   (ts <= s (1 + 2^-24),
+  //       one rounding of 2^-24 either side; eu covers the negative case),
+  //   K = fl(ts ru + eu) >= s ratio (1 + 2^-23) + E   (ts >= s (1 - 2^-24)).
+  // S~ <= P gives S(i, j) <= T (1 - 2^-50) with T = S(p, j) den^2 / num^2,
+  // hence fl(num^2 S(i, j)) <= fl(den^2 S(p, j)); S~ > K gives
+  // S(i, j) > T (1 + 2^-50), hence the opposite (FP64 roundings of 2^-53).
+  // A subnormal ts adds at most 2^-149, far below E 2^-22 (E > c3).
   float P[NW][NA], K[NW][NA];
   double Ew[NW];
 #pragma unroll
   for (int w = 0; w < NW; ++w) {
     const double E = fa.c1 * s2[w] + fa.c2 * sqrt(s2[w]) + fa.c3;
     Ew[w] = E;
+    const float ts = (float)s2[w];
+    const float eu = f32_up(E * (1.0 + 0x1p-22));
 #pragma unroll
     for (int ai = 0; ai < NA; ++ai) {
-      // t = fl(S(p, j) fl(den^2 / num^2)) is within 2^-51.4 of den^2 S(p, j) / num^2,
-      // so S(i, j) <= t (1 - 2^-50) implies fl(num^2 S(i, j)) <= fl(den^2 S(p, j)),
-      // and S(i, j) > t (1 + 2^-49) implies the opposite.
-      const double t = sw[w] * a.ratio[ai];
-      P[w][ai] = f32_down(t * (1.0 - 0x1p-50) * sc2 - E);
-      K[w][ai] = f32_up(t * (1.0 + 0x1p-49) * sc2 + E);
+      P[w][ai] = __builtin_fmaf(ts, a.ratio_dn[ai], -eu);
+      K[w][ai] = __builtin_fmaf(ts, a.ratio_up[ai], eu);
     }
   }
 
   // Rows that can prune: row i can remove some j > i at alpha_k only if
   // S~(i, j) <= K_k(j), which implies fl(S~(i, j) fl(1 / s_j)) <=
   // fl(K_k(j) fl(1 / s_j)) (the same reciprocal, monotone rounding).  The
-  // right side is at most (ratio_k (1 + 2^-48) + E_j / s_j)(1 + 2^-21): K_k(j)
-  // is t (1 + 2^-49) 2^2e + E_j rounded up, t = fl(S(p, j) ratio_k), with
-  // FP64 roundings of 2^-53 and FP32 ones of 2^-24 (K is a normal float: it
-  // exceeds c3).  So with eps >= max_j E_j / s_j,
-  // kappa_k = (ratio_k (1 + 2^-48) + eps)(1 + 2^-20) rounded up bounds every
+  // right side is at most (ratio_k + E_j / s_j)(1 + 2^-20.5): K_k(j) =
+  // fl(ts ru + eu) with ru <= ratio_k (1 + 2^-22)(1 + 2^-23), eu <=
+  // E_j (1 + 2^-22)(1 + 2^-23)(1 + 2^-53), and FP32 roundings of 2^-24 in ts,
+  // K, the reciprocal and the product (K is a normal float: it exceeds c3).
+  // So with eps >= max_j E_j / s_j,
+  // kappa_k = (ratio_k (1 + 2^-48) + eps)(1 + 2^-19) rounded up bounds every
   // such product, and zmin_i = min_j fl(S~(i, j) fl(1 / s_j)) <= kappa_k
   // holds for every row that can prune (one reduction serves all alphas; a
   // looser bound only adds rows to visit).  Empty ranks have a NaN
@@ -739,6 +748,7 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
   uint64_t vis[NA][NW];
   {
     float inv[NW];
+    wave_sync();  // the tile's reads of S(p, .) are done before the region is reused
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
       inv[w] = valid[w] ? (s2[w] > 0.0 ? (float)(1.0 / s2[w]) : 0.f) : __builtin_nanf("");
@@ -765,7 +775,7 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
     for (int off = 32; off > 0; off >>= 1) eps = fmaxf(eps, __shfl_xor(eps, off, 64));
 #pragma unroll
     for (int ai = 0; ai < NA; ++ai) {
-      const float kappa = f32_up((a.ratio[ai] * (1.0 + 0x1p-48) + (double)eps) * (1.0 + 0x1p-20));
+      const float kappa = f32_up((a.ratio[ai] * (1.0 + 0x1p-48) + (double)eps) * (1.0 + 0x1p-19));
 #pragma unroll
       for (int w = 0; w < NW; ++w) vis[ai][w] = __ballot(valid[w] && zmin[w] <= kappa);
     }
@@ -1134,6 +1144,19 @@ struct DiagLaunch {
   }
 };
 
+// FP32 value <= x and >= x (host).
+float host_f32_down(double x) {
+  float f = (float)x;
+  if ((double)f > x) f = std::nextafter(f, -HUGE_VALF);
+  return f;
+}
+
+float host_f32_up(double x) {
+  float f = (float)x;
+  if ((double)f < x) f = std::nextafter(f, HUGE_VALF);
+  return f;
+}
+
 // Sorts the alphas of a sweep in descending order (num_a^2 den_b^2 against
 // num_b^2 den_a^2) and moves every output with its alpha (outputs are
 // alpha-major: o = alpha * nr + iR).
@@ -1195,8 +1218,14 @@ hipError_t launch_prune_f32(const GraphView& g, const SweepArgs& a_in, DevCounte
   if (a_in.n_alpha < 1 || a_in.n_out % a_in.n_alpha != 0) return hipErrorInvalidValue;
   F32Args fa = {};
   fa.nr = a_in.n_out / a_in.n_alpha;
-  // the kernel takes the alphas in descending order
-  const SweepArgs a = alphas_descending(a_in, fa.nr);
+  // the kernel takes the alphas in descending order, with FP32 bounds of
+  // each ratio den^2 / num^2 (within (1 -/+ 2^-22))
+  SweepArgs a = alphas_descending(a_in, fa.nr);
+  for (int k = 0; k < a.n_alpha; ++k) {
+    const double x = (double)a.den2[k] / (double)a.num2[k];  // within 2^-53 of the ratio
+    a.ratio_dn[k] = host_f32_down(x * (1.0 - 0x1p-22) * (1.0 - 0x1p-50));
+    a.ratio_up[k] = host_f32_up(x * (1.0 + 0x1p-22) * (1.0 + 0x1p-50));
+  }
   const Plan pl = plan_of(g);
   f32_bound_constants(g.d, pl.csum, &fa.c1, &fa.c2, &fa.c3);
   return dispatch<SweepLaunch>(pl, g, a, fa, ctr, s);

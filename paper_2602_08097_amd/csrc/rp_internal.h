@@ -34,6 +34,9 @@ struct SweepArgs {
   uint32_t num2[kMaxAlphas];
   uint32_t den2[kMaxAlphas];
   double ratio[kMaxAlphas];  // den^2 / num^2 rounded to FP64 (a first guess only)
+  // FP32 bounds of den^2 / num^2 below and above (float32 kernel; set by its launcher)
+  float ratio_dn[kMaxAlphas];
+  float ratio_up[kMaxAlphas];
   int32_t n_alpha;
   int32_t n_out;
   SweepOut out[kMaxOutputs];
