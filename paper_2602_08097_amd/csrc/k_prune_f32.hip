@@ -24,7 +24,8 @@
 //              otherwise the keys are sorted and the rows are streamed a
 //              second time in rank order.  Repeated ids are dropped.
 //  a5  Gram:   in the frame centred on p and scaled by 2^e (every scaled
-//              difference below 2^14; e from the per-point max |x_k|), each
+//              difference below 2^14; e of each vertex is computed with the
+//              graph from the max |x_k| of the vertex and its list), each
 //              FP32 difference is split as hi + lo, two FP16 values, and
 //              G~ = sum hi hi' + hi lo' + lo hi' runs on
 //              v_mfma_f32_32x32x16_f16; for long rows the accumulator restarts
@@ -476,11 +477,9 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
     }
     mq = g.deg[q];
   };
-  // usable ids, this lane's rows, and the loads vertex q starts with: scale
-  // inputs, x_p, then the first steps of the rows
+  // usable ids, this lane's rows, and the first steps of the rows
   int idw[NW];
   const float* rows[NB];
-  float mjl = 0.f, mp = 0.f;
   int fe = 0;
   float4 xv;
   Ring<NB> ring;
@@ -495,18 +494,12 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
       const int id = b < 2 ? __shfl(idw[0], 32 * b + l32, 64) : __shfl(idw[NW - 1], l32, 64);
       rows[b] = X + (int64_t)(id >= 0 ? id : (int)q) * d;
     }
-    mjl = 0.f;
-    if (g.frame_e == nullptr) {  // uniform: no frame exponents with the graph
-#pragma unroll
-      for (int w = 0; w < NW; ++w)
-        if (idw[w] >= 0) mjl = fmaxf(mjl, g.maxabs[idw[w]]);
-      mp = g.maxabs[q];
-    }
     ring_fill<NB, VEC, PF>(ring, rows, d, half);
   };
-  // loads that do not wait for the list: x_p and the frame exponent
+  // loads that do not wait for the list: x_p and the vertex's frame exponent
+  // (computed with the graph from its list and the per-point max |x_k|)
   auto early = [&](int64_t q) {
-    if (g.frame_e != nullptr) fe = g.frame_e[q];
+    fe = g.frame_e[q];
     const float* xrow = X + q * d;
     xv = make_float4(0.f, 0.f, 0.f, 0.f);
     if (VEC) {
@@ -529,12 +522,7 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
   unsigned long long dg_pairs = 0;
   const int nbu = max(1, min(NB, (m + 31) >> 5));  // uniform: blocks holding listed slots
 
-  int e = fe;
-  if (g.frame_e == nullptr) {
-    float mj = mjl;
-    for (int off = 32; off > 0; off >>= 1) mj = fmaxf(mj, __shfl_xor(mj, off, 64));
-    e = frame_exponent(mj + mp);
-  }
+  const int e = fe;
   const float scf = ldexpf(1.f, e);
   const double sc = ldexp(1.0, e);
   const double sc2 = sc * sc;
@@ -1198,6 +1186,7 @@ bool prune_f32_supported(const GraphView& g) {
 hipError_t launch_gram_error_f32(const GraphView& g, const int32_t* nodes, int64_t n_nodes,
                                  GramErrorStats* stats, DevCounters* ctr, hipStream_t s) {
   if (n_nodes == 0) return hipSuccess;
+  if (g.frame_e == nullptr) return hipErrorInvalidValue;  // set by graph load / derive
   SweepArgs a = {};
   a.n_alpha = 1;
   a.n_out = 0;
@@ -1216,6 +1205,7 @@ hipError_t launch_gram_error_f32(const GraphView& g, const int32_t* nodes, int64
 hipError_t launch_prune_f32(const GraphView& g, const SweepArgs& a_in, DevCounters* ctr,
                             hipStream_t s) {
   if (a_in.n_alpha < 1 || a_in.n_out % a_in.n_alpha != 0) return hipErrorInvalidValue;
+  if (g.frame_e == nullptr) return hipErrorInvalidValue;  // set by graph load / derive
   F32Args fa = {};
   fa.nr = a_in.n_out / a_in.n_alpha;
   // the kernel takes the alphas in descending order, with FP32 bounds of
