@@ -795,49 +795,56 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
   // below).
   if constexpr (NW == 1) {
     // Alphas arrive in descending order, so chains visit ever more rows:
-    // phase s0 advances chains s0..NA-1 while chain s0 has survivors (a
-    // finished chain repeats harmless empty steps).
+    // phase s0 advances chains s0..end of its group while chain s0 has
+    // survivors (a finished chain repeats harmless empty steps).  Groups of
+    // four chains run one after the other, so a group's masks stay in scalar
+    // registers.
+    constexpr int GS = 4;
 #pragma unroll
-    for (int s0 = 0; s0 < NA; ++s0) {
-      while (uniform_u64(alive[s0][0]) != 0) {
-        float row[NA];
-        int istar[NA];
+    for (int g0 = 0; g0 < NA; g0 += GS) {
+      const int g1 = g0 + GS < NA ? g0 + GS : NA;
 #pragma unroll
-        for (int ai = s0; ai < NA; ++ai) {
-          const uint64_t al = uniform_u64(alive[ai][0]);
-          const int i = ff1_u64(al & vis[ai][0]);
-          // ranks above i; with no candidate (i = -1, shift 63) none, so
-          // every survivor is kept and the chain ends
-          const uint64_t above = 0xFFFFFFFFFFFFFFFEull << (i & 63);
-          const uint64_t k = uniform_u64(kept[ai][0]) | (al & ~above);
-          kept[ai][0] = k;
-          alive[ai][0] = (CAP && __popcll(k) >= rmax[ai]) ? 0ull : al & above;
-          istar[ai] = i & 63;
-          row[ai] = St[(i & 63) * 32 + lbase[0]];
-        }
-        uint64_t amb[NA];
-        uint64_t any_amb = 0;
+      for (int s0 = g0; s0 < g1; ++s0) {
+        while (uniform_u64(alive[s0][0]) != 0) {
+          float row[NA];
+          int istar[NA];
 #pragma unroll
-        for (int ai = s0; ai < NA; ++ai) {
-          const uint64_t pm = __ballot(row[ai] <= P[0][ai]);
-          amb[ai] = __ballot(row[ai] <= K[0][ai]) & ~pm & alive[ai][0];
-          alive[ai][0] &= ~pm;
-          any_amb |= amb[ai];
-        }
-        if (uniform_u64(any_amb) != 0) {
+          for (int ai = s0; ai < g1; ++ai) {
+            const uint64_t al = uniform_u64(alive[ai][0]);
+            const int i = ff1_u64(al & vis[ai][0]);
+            // ranks above i; with no candidate (i = -1, shift 63) none, so
+            // every survivor is kept and the chain ends
+            const uint64_t above = 0xFFFFFFFFFFFFFFFEull << (i & 63);
+            const uint64_t k = uniform_u64(kept[ai][0]) | (al & ~above);
+            kept[ai][0] = k;
+            alive[ai][0] = (CAP && __popcll(k) >= rmax[ai]) ? 0ull : al & above;
+            istar[ai] = i & 63;
+            row[ai] = St[(i & 63) * 32 + lbase[0]];
+          }
+          uint64_t amb[NA];
+          uint64_t any_amb = 0;
 #pragma unroll
-          for (int ai = s0; ai < NA; ++ai) {
-            const uint64_t am = uniform_u64(amb[ai]);
-            if (am) {
-              const int pid = __builtin_amdgcn_readlane(id_rank[0], istar[ai]);
-              bool prune = false;
-              if ((am >> lane) & 1ull) {
-                const double sx =
-                    canon_rows<VEC>(X + (int64_t)pid * d, X + (int64_t)id_rank[0] * d, d);
-                prune = alpha_test_f64(a.num2[ai], a.den2[ai], sx, sw[0]);
+          for (int ai = s0; ai < g1; ++ai) {
+            const uint64_t pm = __ballot(row[ai] <= P[0][ai]);
+            amb[ai] = __ballot(row[ai] <= K[0][ai]) & ~pm & alive[ai][0];
+            alive[ai][0] &= ~pm;
+            any_amb |= amb[ai];
+          }
+          if (uniform_u64(any_amb) != 0) {
+#pragma unroll
+            for (int ai = s0; ai < g1; ++ai) {
+              const uint64_t am = uniform_u64(amb[ai]);
+              if (am) {
+                const int pid = __builtin_amdgcn_readlane(id_rank[0], istar[ai]);
+                bool prune = false;
+                if ((am >> lane) & 1ull) {
+                  const double sx =
+                      canon_rows<VEC>(X + (int64_t)pid * d, X + (int64_t)id_rank[0] * d, d);
+                  prune = alpha_test_f64(a.num2[ai], a.den2[ai], sx, sw[0]);
+                }
+                alive[ai][0] &= ~(uint64_t)__ballot(prune);
+                rechecks += __popcll(am);
               }
-              alive[ai][0] &= ~(uint64_t)__ballot(prune);
-              rechecks += __popcll(am);
             }
           }
         }
