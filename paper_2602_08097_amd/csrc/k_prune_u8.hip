@@ -12,9 +12,11 @@
 //              load each, all in flight together -- shifted to int8
 //              u = x - 128 (the shift leaves every difference unchanged).
 //              No LDS staging.
-//  a3  p-row:  S(p, j) = |u_p|^2 + |u_j|^2 - 2 <u_p, u_j>, exact in int32,
-//              with 4-way int8 dot products on the same registers (the two
-//              halves of a row are combined across lanes l and l + 32).
+//  a3  p-row:  S(p, j) = |u_p|^2 + |u_j|^2 - 2 <u_p, u_j>, exact in int32:
+//              |u_j|^2 by 4-way int8 dot products on the same registers (the
+//              two halves of a row combined across lanes l and l + 32),
+//              <u_p, u_j> and |u_p|^2 on the matrix unit with x_p in every row
+//              of the left operand.
 //  a4  sort:   keys (S(p, j), id, slot) packed in 64 bits.  A list already in
 //              (S, id) order -- every RobustPrune output is -- keeps its rows
 //              where they are; otherwise a 64-lane bitonic sort (DPP and
@@ -27,9 +29,11 @@
 //              block at a time, blocks on and above the diagonal only.
 //  a6  test:   alpha * D(p*, p') <= D(p, p') on squares is
 //              num^2 S(p*, p') <= den^2 S(p, p')  <=>  S(p*, p') <= T(p'),
-//              T(p') = floor(den^2 S(p, p') / num^2), exact for integer S.
-//              With the alphas ascending, the alphas that prune p' from p*
-//              are a prefix 0..c-1; the 3 KiB decision tile stores 2^c - 1.
+//              T(p') = floor(den^2 S(p, p') / num^2), exact for integer S
+//              (one 64-bit reciprocal multiply).  With the alphas ascending,
+//              the alphas that prune p' from p* are a prefix 0..c-1; the
+//              3 KiB decision tile stores 2^c - 1, summed from one median per
+//              alpha.
 //  a7  greedy: per alpha a 64-bit survivor mask.  Survivors whose row prunes
 //              nothing at that alpha are kept in runs; each survivor whose row
 //              can prune is kept and one ballot over its tile row removes what
@@ -48,18 +52,51 @@ namespace {
 
 constexpr int kDecisionBytes = 3072;  // decision tile: the blocks on and above the diagonal
 constexpr int kMaxDimU8 = 256;
-constexpr int kWaveLdsU8 = kDecisionBytes + 64 * 4;  // + |u|^2 by rank
+constexpr int kWaveLdsU8 = kDecisionBytes + 64 * 4;  // + -16 |u|^2 by rank
 
-// floor(den2 * s / num2) for s < 2^28, exact: s * fl(den2 / num2) is within
-// 2^-24 of the quotient, so one integer correction step settles it.
-__device__ __forceinline__ int32_t alpha_threshold(uint32_t num2, uint32_t den2, double ratio,
-                                                   uint32_t s) {
-  const uint64_t B = (uint64_t)den2 * s;
-  uint32_t t = (uint32_t)((double)s * ratio);
-  const uint64_t nt = (uint64_t)num2 * t;
-  if (nt > B) t -= 1;
-  else if (nt + num2 <= B) t += 1;
-  return (int32_t)t;
+// floor(den2 * s / num2) for s < 2^28, exact, from M = floor(2^60 den2 / num2) + 1:
+// 0 < s (M / 2^60 - den2 / num2) < 2^-32 < 1 / num2, less than the gap between a
+// non-integer quotient and the next integer, so floor(16 s M / 2^64) is the
+// floor (two 32 x 32 -> 64-bit multiply-adds).
+__device__ __forceinline__ int32_t alpha_threshold(uint64_t M, uint32_t s) {
+  const uint64_t s16 = (uint64_t)(s << 4);
+  const uint64_t lo = s16 * (uint64_t)(uint32_t)M;
+  const uint64_t hi = s16 * (M >> 32) + (lo >> 32);
+  return (int32_t)(uint32_t)(hi >> 32);
+}
+
+// The decision bounds of this lane's tile column j.  Pair (i, j) is pruned at
+// alpha_k  <=>  S(i, j) <= T_k(j)  <=>  y = 2 G(i, j) - |u_i|^2 >= U_k = |u_j|^2 - T_k(j).
+// On Y = 16 y with B_k = 16 U_k and A_k = B_k - w_k, w_k = 2^(k mod 4), the median
+// med3(Y, A_k, B_k) - A_k is w_k when Y >= B_k and 0 otherwise (Y and B_k are
+// multiples of 16 > w_k), so the code 2^c - 1 is a sum of medians offset by
+// -sum A_k: alphas 0..3 in the low nibble, 4..7 in the high one.
+template <int NA>
+struct ColBounds {
+  int32_t A[NA], B[NA];
+  int32_t off_lo, off_hi;
+};
+
+template <int NA>
+__device__ __forceinline__ ColBounds<NA> col_bounds(int32_t ncol16, const int32_t (&T)[NA]) {
+  ColBounds<NA> cb;
+  cb.off_lo = 0;
+  cb.off_hi = 0;
+#pragma unroll
+  for (int k = 0; k < NA; ++k) {
+    cb.B[k] = ncol16 - 16 * T[k];
+    cb.A[k] = cb.B[k] - (1 << (k & 3));
+    if (k < 4) cb.off_lo -= cb.A[k];
+    else cb.off_hi -= cb.A[k];
+  }
+  return cb;
+}
+
+// One v_med3_i32 (the compiler keeps min(max()) of register bounds as two).
+__device__ __forceinline__ int32_t med3_i32(int32_t x, int32_t lo, int32_t hi) {
+  int32_t r;
+  asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
+  return r;
 }
 
 // a1: the list of p (row and degree loads in flight together).
@@ -107,13 +144,8 @@ __device__ __forceinline__ int sdot16(v4i a, v4i b, int acc) {
 // register v.
 template <int NA, int BI, int BJ>
 __device__ __forceinline__ void decide_block(uint8_t* C, const int32_t* mnr, const v16i& acc,
-                                             const int32_t (&T)[NA], int l32, int half) {
-  // S(i, j) <= T_k(j)  <=>  y = 2 G(i, j) - |u_i|^2 >= U_k = |u_j|^2 - T_k(j)
-  const int32_t ncol = -mnr[32 * BJ + l32];
-  int32_t U[NA];
-#pragma unroll
-  for (int k = 0; k < NA; ++k) U[k] = ncol - T[k];
-  // -|u|^2 of this lane's 16 rows: rows 8 q + 4 half + 0..3 are consecutive
+                                             const ColBounds<NA>& cb, int l32, int half) {
+  // -16 |u|^2 of this lane's 16 rows: rows 8 q + 4 half + 0..3 are consecutive
   int4 nrow[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) nrow[q] = *(const int4*)(mnr + 32 * BI + 8 * q + 4 * half);
@@ -124,14 +156,20 @@ __device__ __forceinline__ void decide_block(uint8_t* C, const int32_t* mnr, con
   for (int v = 0; v < 16; ++v) {
     const int rr = 8 * (v >> 2) + (v & 3);  // r - 4 half, a constant
     const int4 nq = nrow[v >> 2];
-    const int32_t mn = (v & 3) == 0 ? nq.x : (v & 3) == 1 ? nq.y : (v & 3) == 2 ? nq.z : nq.w;
-    const int32_t y = 2 * acc[v] + mn;
-    // U_k ascends with k, so the alphas that prune are 0..c-1 and the code
-    // 2^c - 1 is the last 2^(k+1) - 1 with y >= U_k (a compare and a select per
-    // alpha)
-    uint32_t t = 0;
+    const int32_t mn16 = (v & 3) == 0 ? nq.x : (v & 3) == 1 ? nq.y : (v & 3) == 2 ? nq.z : nq.w;
+    const int32_t Y = acc[v] * 32 + mn16;  // 16 y
+    // U_k ascends with k, so the alphas that prune are 0..c-1 and the sum of
+    // medians is the code 2^c - 1
+    int32_t lo = cb.off_lo;
 #pragma unroll
-    for (int k = 0; k < NA; ++k) t = y >= U[k] ? (2u << k) - 1u : t;
+    for (int k = 0; k < (NA < 4 ? NA : 4); ++k) lo += med3_i32(Y, cb.A[k], cb.B[k]);
+    uint32_t t = (uint32_t)lo;
+    if (NA > 4) {
+      int32_t hi = cb.off_hi;
+#pragma unroll
+      for (int k = 4; k < NA; ++k) hi += med3_i32(Y, cb.A[k], cb.B[k]);
+      t += (uint32_t)hi << 4;
+    }
     if (BI == BJ) t = below > rr ? t : 0u;
     base[32 * rr] = (uint8_t)t;
   }
@@ -187,20 +225,38 @@ __device__ __forceinline__ Front node_front(uint8_t* C, int32_t* nr, const Graph
   }
 
   // ---- a3: p-row S(p, j) and |u_j|^2 -------------------------------------
-  int n0 = 0, n1 = 0, q0 = 0, q1 = 0, np = 0;
+  // <u_p, u_j> and |u_p|^2 on the matrix unit: with x_p in every row of the
+  // left operand, every row of the product is the p-row of inner products
+  int n0 = 0, n1 = 0;
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
     n0 = sdot16(f0[k], f0[k], n0);
     n1 = sdot16(f1[k], f1[k], n1);
-    q0 = sdot16(f0[k], fp[k], q0);
-    q1 = sdot16(f1[k], fp[k], q1);
-    np = sdot16(fp[k], fp[k], np);
   }
   n0 += __shfl_xor(n0, 32, 64);
   n1 += __shfl_xor(n1, 32, 64);
-  q0 += __shfl_xor(q0, 32, 64);
-  q1 += __shfl_xor(q1, 32, 64);
-  np += __shfl_xor(np, 32, 64);
+  int q0, q1, np;
+  {
+    v16i acc = {0};
+#pragma unroll
+    for (int k = 0; k < NK; ++k)
+      acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(fp[k], f0[k], acc, 0, 0, 0);
+    q0 = acc[0];
+  }
+  {
+    v16i acc = {0};
+#pragma unroll
+    for (int k = 0; k < NK; ++k)
+      acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(fp[k], f1[k], acc, 0, 0, 0);
+    q1 = acc[0];
+  }
+  {
+    v16i acc = {0};
+#pragma unroll
+    for (int k = 0; k < NK; ++k)
+      acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(fp[k], fp[k], acc, 0, 0, 0);
+    np = acc[0];
+  }
   // lane l is slot l: block 0 for l < 32, block 1 for l >= 32
   const int32_t nj = half ? n1 : n0;
   const uint32_t sp = (uint32_t)(np + nj - 2 * (half ? q1 : q0));
@@ -240,40 +296,44 @@ __device__ __forceinline__ Front node_front(uint8_t* C, int32_t* nr, const Graph
   const int slot = (int)(key & 63);
   const uint32_t s_rank = valid ? (uint32_t)(key >> shift) : 0u;
   f.id_rank = valid ? (int)((key >> 6) & ((1ull << idbits) - 1)) : -1;
-  nr[lane] = -__shfl(nj, slot, 64);  // -|u|^2 by rank
+  const int32_t n_rank = __shfl(nj, slot, 64);
+  nr[lane] = -16 * n_rank;  // -16 |u|^2 by rank
 
-  // ---- a6: thresholds of this rank, then of the lane's two tile columns ---
+  // ---- a6: thresholds of this rank, then the bounds of the lane's two tile
+  // columns (l32 and 32 + l32)
   int32_t T0[NA], T1[NA];
 #pragma unroll
   for (int k = 0; k < NA; ++k) {
-    const int32_t t = alpha_threshold(a.num2[k], a.den2[k], a.ratio[k], s_rank);
-    T0[k] = __shfl(t, l32, 64);        // column l32
-    T1[k] = __shfl(t, 32 + l32, 64);   // column 32 + l32
+    const int32_t t = alpha_threshold(a.thr_mul[k], s_rank);
+    T0[k] = __shfl(t, l32, 64);
+    T1[k] = __shfl(t, 32 + l32, 64);
   }
+  const ColBounds<NA> cb0 = col_bounds<NA>(16 * __shfl(n_rank, l32, 64), T0);
+  const ColBounds<NA> cb1 = col_bounds<NA>(16 * __shfl(n_rank, 32 + l32, 64), T1);
   wave_sync();  // the |u|^2 table is visible
 
   // ---- a5: Gram blocks on MFMA (rank order), then their decision codes ----
-  const int nk = (d + 31) >> 5;
+  // (every step runs: slices past d are zero)
   {
     v16i acc = {0};
 #pragma unroll
     for (int k = 0; k < NK; ++k)
-      if (k < nk) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(f0[k], f0[k], acc, 0, 0, 0);
-    decide_block<NA, 0, 0>(C, nr, acc, T0, l32, half);
+      acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(f0[k], f0[k], acc, 0, 0, 0);
+    decide_block<NA, 0, 0>(C, nr, acc, cb0, l32, half);
   }
   {
     v16i acc = {0};
 #pragma unroll
     for (int k = 0; k < NK; ++k)
-      if (k < nk) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(f0[k], f1[k], acc, 0, 0, 0);
-    decide_block<NA, 0, 1>(C, nr, acc, T1, l32, half);
+      acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(f0[k], f1[k], acc, 0, 0, 0);
+    decide_block<NA, 0, 1>(C, nr, acc, cb1, l32, half);
   }
   {
     v16i acc = {0};
 #pragma unroll
     for (int k = 0; k < NK; ++k)
-      if (k < nk) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(f1[k], f1[k], acc, 0, 0, 0);
-    decide_block<NA, 1, 1>(C, nr, acc, T1, l32, half);
+      acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(f1[k], f1[k], acc, 0, 0, 0);
+    decide_block<NA, 1, 1>(C, nr, acc, cb1, l32, half);
   }
   return f;
 }
@@ -393,7 +453,7 @@ __global__ __launch_bounds__(512) void prune_u8_kernel(GraphView g, SweepArgs a,
   if (p >= g.n) return;
   uint8_t* lds = lds_all + (size_t)wave * wave_lds;
   uint8_t* C = lds;                                 // decision tile
-  int32_t* nr = (int32_t*)(lds + kDecisionBytes);  // -|u|^2 by rank
+  int32_t* nr = (int32_t*)(lds + kDecisionBytes);  // -16 |u|^2 by rank
   const Front f = node_front<NA, NK>(C, nr, g, a, p, lane, idbits);
   wave_sync();  // the decision tile is visible
   node_back<NA, CAP>(C, a, p, f, lane, nr_out);
@@ -460,6 +520,7 @@ hipError_t launch_prune_u8(const GraphView& g, const SweepArgs& a_in, DevCounter
     a.num2[k] = a_in.num2[order[k]];
     a.den2[k] = a_in.den2[order[k]];
     a.ratio[k] = a_in.ratio[order[k]];
+    a.thr_mul[k] = (uint64_t)((((unsigned __int128)a.den2[k]) << 60) / a.num2[k]) + 1u;
     for (int ir = 0; ir < nr; ++ir) {
       a.out[k * nr + ir] = a_in.out[order[k] * nr + ir];
       a.out[k * nr + ir].alpha_idx = k;

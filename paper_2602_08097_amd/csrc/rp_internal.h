@@ -37,6 +37,8 @@ struct SweepArgs {
   // FP32 bounds of den^2 / num^2 below and above (float32 kernel; set by its launcher)
   float ratio_dn[kMaxAlphas];
   float ratio_up[kMaxAlphas];
+  // floor(2^60 den^2 / num^2) + 1 (uint8 kernel; set by its launcher)
+  uint64_t thr_mul[kMaxAlphas];
   int32_t n_alpha;
   int32_t n_out;
   SweepOut out[kMaxOutputs];
