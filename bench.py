@@ -152,8 +152,9 @@ MFMA_PEAK = {"u8": 5000.0, "f32": 2500.0}  # dense int8 TOP/s, fp16 TFLOP/s
 
 def mfma_usage(dtype, deg, d, r_max, kernel_ms):
     """Matrix-unit work of one sweep launch: the executed MFMA operations of
-    the batched kernel (uint8: three 32 x 32 x 32 int8 blocks per vertex and
-    32-dimension step; float32: the blocks on and above the diagonal of the
+    the batched kernel (uint8: six 32 x 32 x 32 int8 products per vertex and
+    32-dimension step, three Gram blocks and three with x_p in every row, over
+    4 steps for d <= 128 and 8 above; float32: the blocks on and above the diagonal of the
     row blocks in use, three 32 x 32 x 16 FP16 products per 16-dimension step)
     and the Gram's useful work (one product per candidate pair above the
     diagonal), each over the kernel's mean time, against the dense peak."""
@@ -161,8 +162,8 @@ def mfma_usage(dtype, deg, d, r_max, kernel_ms):
 
     m = deg.astype(np.int64)
     if dtype == np.uint8:
-        steps = (d + 31) // 32
-        executed = int(m.shape[0]) * 3 * steps * (32 * 32 * 32 * 2)
+        steps = 4 if d <= 128 else 8
+        executed = int(m.shape[0]) * 6 * steps * (32 * 32 * 32 * 2)
         key, unit = "u8", "TOP/s"
     else:
         nbu = np.maximum(1, np.minimum((r_max + 31) // 32, (m + 31) // 32))

@@ -137,8 +137,9 @@ __device__ __forceinline__ int sdot16(v4i a, v4i b, int acc) {
 }
 
 // The decision codes of one 32 x 32 block (rows of block BI, columns of block
-// BJ) from its Gram accumulator; the diagonal blocks keep only columns after
-// the row.  Tile layout: columns 0..31 of rows 0..31 at byte 32 i + c; columns
+// BJ) from its Gram accumulator.  The diagonal blocks also code the columns up
+// to the row; those ranks are never alive when the row is visited, and the
+// row scan of the greedy drops them.  Tile layout: columns 0..31 of rows 0..31 at byte 32 i + c; columns
 // 32..63 of rows 0..63 at byte 1024 + 32 i + (c - 32).  Accumulator layout:
 // lane l holds column l % 32 of rows 8 (v / 4) + 4 (l / 32) + v % 4 in
 // register v.
@@ -151,7 +152,6 @@ __device__ __forceinline__ void decide_block(uint8_t* C, const int32_t* mnr, con
   for (int q = 0; q < 4; ++q) nrow[q] = *(const int4*)(mnr + 32 * BI + 8 * q + 4 * half);
   // row r = 8 q + 4 half + j of the block is byte base + 32 (8 q + j)
   uint8_t* base = C + (BJ == 0 ? 0 : 1024 + 32 * 32 * BI) + 128 * half + l32;
-  const int below = l32 - 4 * half;  // column after row  <=>  below > 8 q + j
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
     const int rr = 8 * (v >> 2) + (v & 3);  // r - 4 half, a constant
@@ -170,7 +170,6 @@ __device__ __forceinline__ void decide_block(uint8_t* C, const int32_t* mnr, con
       for (int k = 4; k < NA; ++k) hi += med3_i32(Y, cb.A[k], cb.B[k]);
       t += (uint32_t)hi << 4;
     }
-    if (BI == BJ) t = below > rr ? t : 0u;
     base[32 * rr] = (uint8_t)t;
   }
 }
@@ -353,17 +352,33 @@ __device__ __forceinline__ void node_back(const uint8_t* C, const SweepArgs& a, 
       for (int ir = 0; ir < NR; ++ir) rmax[ai] = max(rmax[ai], a.out[ai * NR + ir].R);
     }
   }
-  // Rows that prune anything, per chain: the OR of row i's codes (lane i).
-  // Columns 0..31 of rows 0..31 are at bytes 32 i ..; columns 32..63 of every
-  // row at 1024 + 32 i ...
+  // Rows that prune anything, per chain: the OR of row i's codes (lane i) over
+  // the columns after i.  Columns 0..31 of rows 0..31 are at bytes 32 i ..;
+  // columns 32..63 of every row at 1024 + 32 i ...
   uint64_t vis[NA];
   {
-    uint4 r0 = *(const uint4*)(C + 1024 + 32 * lane);
-    uint4 r1 = *(const uint4*)(C + 1024 + 32 * lane + 16);
-    uint32_t acc = r0.x | r0.y | r0.z | r0.w | r1.x | r1.y | r1.z | r1.w;
+    // the lane's row in its diagonal block, less its first (i % 32) + 1 bytes
+    const uint8_t* drow = C + (lane < 32 ? 32 * lane : 1024 + 32 * lane);
+    const uint4 d0 = *(const uint4*)drow;
+    const uint4 d1 = *(const uint4*)(drow + 16);
+    const uint64_t q[4] = {(uint64_t)d0.y << 32 | d0.x, (uint64_t)d0.w << 32 | d0.z,
+                           (uint64_t)d1.y << 32 | d1.x, (uint64_t)d1.w << 32 | d1.z};
+    const int drop = 8 * ((lane & 31) + 1);  // bits
+    uint64_t acc64 = 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (NA < 8) {
+        // a word dropped whole keeps only its bit 63, code bit 7: unused below 8 alphas
+        acc64 |= q[t] >> min(max(drop - 64 * t, 0), 63);
+      } else {
+        const int h = min(max(drop - 64 * t, 0), 64) >> 1;
+        acc64 |= (q[t] >> h) >> h;
+      }
+    }
+    uint32_t acc = (uint32_t)acc64 | (uint32_t)(acc64 >> 32);
     if (lane < 32) {
-      r0 = *(const uint4*)(C + 32 * lane);
-      r1 = *(const uint4*)(C + 32 * lane + 16);
+      const uint4 r0 = *(const uint4*)(C + 1024 + 32 * lane);
+      const uint4 r1 = *(const uint4*)(C + 1024 + 32 * lane + 16);
       acc |= r0.x | r0.y | r0.z | r0.w | r1.x | r1.y | r1.z | r1.w;
     }
     acc |= acc >> 16;
