@@ -401,7 +401,8 @@ __device__ __forceinline__ void node_back(const uint8_t* C, const SweepArgs& a, 
   // running) has survivors; a finished chain repeats harmless empty steps.
 #pragma unroll
   for (int s0 = NA - 1; s0 >= 0; --s0) {
-    while (uniform_u64(alive[s0]) != 0) {
+    if (uniform_u64(alive[s0]) == 0) continue;
+    do {
       uint32_t row[NA];
 #pragma unroll
       for (int ai = 0; ai <= s0; ++ai) {
@@ -420,7 +421,7 @@ __device__ __forceinline__ void node_back(const uint8_t* C, const SweepArgs& a, 
 #pragma unroll
       for (int ai = 0; ai <= s0; ++ai)
         alive[ai] &= ~(uint64_t)__ballot(row[ai] >= (1u << ai));
-    }
+    } while (uniform_u64(alive[s0]) != 0);
   }
   // a chain that reached its R keeps its first R ranks
 #pragma unroll
