@@ -805,7 +805,9 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
       const int g1 = g0 + GS < NA ? g0 + GS : NA;
 #pragma unroll
       for (int s0 = g0; s0 < g1; ++s0) {
-        while (uniform_u64(alive[s0][0]) != 0) {
+        // tested at the bottom, so the masks stay in place across steps
+        if (uniform_u64(alive[s0][0]) == 0) continue;
+        do {
           float row[NA];
           int istar[NA];
 #pragma unroll
@@ -847,7 +849,7 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
               }
             }
           }
-        }
+        } while (uniform_u64(alive[s0][0]) != 0);
       }
     }
   } else {
