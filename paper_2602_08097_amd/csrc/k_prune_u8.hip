@@ -435,16 +435,23 @@ __device__ __forceinline__ void node_back(const uint8_t* C, const SweepArgs& a, 
   }
 
   // ---- a8: write every output -------------------------------------------
+  // One store per output row: a kept rank goes to its position (the kept
+  // ranks before it), every other lane, in lane order, to the next -1 slot
+  // after the kept ones (there are enough of them for the first 64 slots).
   auto write_out = [&](const SweepOut& out, int ai) {
     const uint64_t km = kept[ai];
     const int tot = __popcll(km);
     const bool mine = (km >> lane) & 1ull;
-    const int pos = __popcll(km & ((1ull << lane) - 1ull));
+    const int before = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
     const int R = out.R;
     const int cntR = tot < R ? tot : R;
     int32_t* orow = out.nbr + p * R;
-    if (mine && pos < R) orow[pos] = f.id_rank;
-    for (int t = cntR + lane; t < R; t += 64) orow[t] = -1;
+    const int pos = mine ? before : cntR + (lane - before);
+    if (pos < R) orow[pos] = mine ? f.id_rank : -1;
+    if (R > 64) {
+      for (int t = 64 + lane; t < R; t += 64) orow[t] = -1;
+    }
     if (lane == 0) out.deg[p] = cntR;
   };
   if (NR == 1) {  // one bound per alpha: fixed argument offsets, loaded together
