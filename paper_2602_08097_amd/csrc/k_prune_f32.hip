@@ -952,6 +952,25 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
 
   // ---- a8: write every output ---------------------------------------------------
   auto write_out = [&](const SweepOut& out, int ai) {
+    if constexpr (NW == 1) {
+      // one store per output row: a kept rank goes to its position, every
+      // other lane, in lane order, to the next -1 slot after the kept ones
+      const uint64_t km = kept[ai][0];
+      const int tot = __popcll(km);
+      const bool mine = (km >> lane) & 1ull;
+      const int before = (int)__builtin_amdgcn_mbcnt_hi(
+          (uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+      const int R = out.R;
+      const int cntR = tot < R ? tot : R;
+      int32_t* orow = out.nbr + p * R;
+      const int pos = mine ? before : cntR + (lane - before);
+      if (pos < R) orow[pos] = mine ? id_rank[0] : -1;
+      if (R > 64) {
+        for (int t = 64 + lane; t < R; t += 64) orow[t] = -1;
+      }
+      if (lane == 0) out.deg[p] = cntR;
+      return;
+    }
     int tot_k = 0, before_w[NW];
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
