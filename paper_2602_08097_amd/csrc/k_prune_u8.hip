@@ -186,24 +186,28 @@ __device__ __forceinline__ Front node_front(uint8_t* C, int32_t* nr, const Graph
 
   // ---- a1 ----------------------------------------------------------------
   const int id = load_list(g, p, lane);
-  const int usable = (id >= 0 && id != (int)p) ? id : -1;
-  const int id0 = __shfl(usable, l32, 64);        // row of block 0 in this lane
-  const int id1 = __shfl(usable, 32 + l32, 64);   // row of block 1
 
   // ---- a2: 16-byte slices of every row, straight into registers ----------
   // every load reads valid memory (absent rows read x_p, slices past d read
-  // the row's last 16 bytes) and is issued unconditionally
+  // the row's last 16 bytes) and is issued unconditionally; x_p's slices go
+  // out while the list is still in flight
   v4i f0[NK], f1[NK], fp[NK];
+  const uint8_t* rp = X + p * d;
+#pragma unroll
+  for (int k = 0; k < NK; ++k) fp[k] = *(const v4i*)(rp + min(32 * k + 16 * half, d - 16));
+  __builtin_amdgcn_sched_barrier(0);
+  const int usable = (id >= 0 && id != (int)p) ? id : -1;
+  const int id0 = __shfl(usable, l32, 64);        // row of block 0 in this lane
+  const int id1 = __shfl(usable, 32 + l32, 64);   // row of block 1
   const uint8_t* r0 = X + (int64_t)(id0 >= 0 ? id0 : (int)p) * d;
   const uint8_t* r1 = X + (int64_t)(id1 >= 0 ? id1 : (int)p) * d;
-  const uint8_t* rp = X + p * d;
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
     const int off = min(32 * k + 16 * half, d - 16);
     f0[k] = *(const v4i*)(r0 + off);
     f1[k] = *(const v4i*)(r1 + off);
-    fp[k] = *(const v4i*)(rp + off);
   }
+  __builtin_amdgcn_sched_barrier(0);  // no use of x_p's slices before every load is out
   // (rows of absent slots hold x_p: their sort keys are invalid, and the codes
   // they produce only ever meet dead survivors)
 #pragma unroll
