@@ -33,7 +33,7 @@ struct SweepOut {
 struct SweepArgs {
   uint32_t num2[kMaxAlphas];
   uint32_t den2[kMaxAlphas];
-  double ratio[kMaxAlphas];  // den^2 / num^2 rounded to FP64 (a first guess only)
+  double ratio[kMaxAlphas];  // den^2 / num^2 rounded to FP64 (float32 kernels)
   // FP32 bounds of den^2 / num^2 below and above (float32 kernel; set by its launcher)
   float ratio_dn[kMaxAlphas];
   float ratio_up[kMaxAlphas];
