@@ -138,9 +138,10 @@ __device__ __forceinline__ int sdot16(v4i a, v4i b, int acc) {
 
 // The decision codes of one 32 x 32 block (rows of block BI, columns of block
 // BJ) from its Gram accumulator.  The diagonal blocks also code the columns up
-// to the row; those ranks are never alive when the row is visited, and the
-// row scan of the greedy drops them.  Tile layout: columns 0..31 of rows 0..31 at byte 32 i + c; columns
-// 32..63 of rows 0..63 at byte 1024 + 32 i + (c - 32).  Accumulator layout:
+// to the row: the greedy masks them off (those ranks are decided before the
+// row is visited) and its row scan drops them.  Tile layout: columns 0..31 of
+// rows 0..31 at byte 32 i + c; columns 32..63 of rows 0..63 at byte
+// 1024 + 32 i + (c - 32).  Accumulator layout:
 // lane l holds column l % 32 of rows 8 (v / 4) + 4 (l / 32) + v % 4 in
 // register v.
 template <int NA, int BI, int BJ>
@@ -390,43 +391,55 @@ __device__ __forceinline__ void node_back(const uint8_t* C, const SweepArgs& a, 
 #pragma unroll
     for (int ai = 0; ai < NA; ++ai) vis[ai] = __ballot((acc >> ai) & 1u) & f.valid_mask;
   }
-  uint64_t alive[NA], kept[NA];
+  // Per chain: rem, the ranks not pruned so far, and cand, the survivors after
+  // the last visited row whose rows can prune.  Every rank up to the visited
+  // row is decided, and a survivor after the last candidate prunes nothing,
+  // so when cand is empty the chain's kept ranks are rem.
+  uint64_t rem[NA], cand[NA], kept[NA];
 #pragma unroll
   for (int ai = 0; ai < NA; ++ai) {
-    alive[ai] = f.valid_mask;
-    kept[ai] = 0;
+    rem[ai] = f.valid_mask;
+    cand[ai] = vis[ai];
   }
   const int lbase = (lane & 31) + 1024 * (lane >> 5);
-  // Chain k: the survivors before the first survivor i whose row can prune
-  // at alpha_k are kept in turn (none removes anything), then i is kept and
-  // row i removes what it prunes; the chain stops at its largest R (trimmed
-  // below).  Chains with larger alpha prune less and visit fewer rows, so
-  // phase s advances chains 0..s while chain s (the largest alpha still
-  // running) has survivors; a finished chain repeats harmless empty steps.
+  // Chain k visits its first candidate i, keeps it with the survivors before
+  // it (none of those prunes anything) and removes what row i prunes; the
+  // chain stops at its largest R (trimmed below).  Chains with larger alpha
+  // prune less and visit fewer rows, so phase s advances chains 0..s while
+  // chain s (the largest alpha still running) has a candidate; a finished
+  // chain repeats harmless empty steps.  The loops test at the bottom, so the
+  // masks stay in place across steps.
 #pragma unroll
   for (int s0 = NA - 1; s0 >= 0; --s0) {
-    if (uniform_u64(alive[s0]) == 0) continue;
+    if (uniform_u64(cand[s0]) == 0) continue;
     do {
       uint32_t row[NA];
+      uint64_t above[NA];
 #pragma unroll
       for (int ai = 0; ai <= s0; ++ai) {
-        const uint64_t al = uniform_u64(alive[ai]);
         int i;
-        const uint64_t cand = al & vis[ai];
-        asm("s_ff1_i32_b64 %0, %1" : "=s"(i) : "s"(cand));
-        // ranks above i; with no candidate (i = -1, shift 63) none, so every
-        // survivor is kept and the chain ends
-        const uint64_t above = 0xFFFFFFFFFFFFFFFEull << (i & 63);
-        const uint64_t k = uniform_u64(kept[ai]) | (al & ~above);
-        kept[ai] = k;
-        alive[ai] = (CAP && __popcll(k) >= rmax[ai]) ? 0ull : al & above;
+        const uint64_t c = uniform_u64(cand[ai]);
+        asm("s_ff1_i32_b64 %0, %1" : "=s"(i) : "s"(c));
+        // ranks after i; with no candidate (i = -1, shift 63) none
+        above[ai] = 0xFFFFFFFFFFFFFFFEull << (i & 63);
         row[ai] = C[(i & 63) * 32 + lbase];
       }
 #pragma unroll
-      for (int ai = 0; ai <= s0; ++ai)
-        alive[ai] &= ~(uint64_t)__ballot(row[ai] >= (1u << ai));
-    } while (uniform_u64(alive[s0]) != 0);
+      for (int ai = 0; ai <= s0; ++ai) {
+        const uint64_t b = __ballot(row[ai] >= (1u << ai));
+        uint64_t ab = above[ai];
+        uint64_t r = uniform_u64(rem[ai]) & ~(b & ab);
+        if (CAP && __popcll(r & ~ab) >= rmax[ai]) {  // R kept up to i: stop
+          r &= ~ab;
+          ab = 0;
+        }
+        rem[ai] = r;
+        cand[ai] = r & ab & vis[ai];
+      }
+    } while (uniform_u64(cand[s0]) != 0);
   }
+#pragma unroll
+  for (int ai = 0; ai < NA; ++ai) kept[ai] = rem[ai];
   // a chain that reached its R keeps its first R ranks
 #pragma unroll
   for (int ai = 0; ai < NA; ++ai) {
