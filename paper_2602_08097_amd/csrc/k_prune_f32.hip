@@ -799,6 +799,14 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
     // survivors (a finished chain repeats harmless empty steps).  Groups of
     // four chains run one after the other, so a group's masks stay in scalar
     // registers.
+    // alive[k][0] holds chain k's ranks not pruned so far and cand[k] its
+    // survivors after the last visited row whose rows can prune; every rank
+    // up to the visited row is decided and a survivor after the last
+    // candidate prunes nothing, so the chain ends when cand is empty and
+    // keeps what is left.
+    uint64_t cand[NA];
+#pragma unroll
+    for (int ai = 0; ai < NA; ++ai) cand[ai] = vis[ai][0] & alive[ai][0];
     constexpr int GS = 4;
 #pragma unroll
     for (int g0 = 0; g0 < NA; g0 += GS) {
@@ -806,20 +814,16 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
 #pragma unroll
       for (int s0 = g0; s0 < g1; ++s0) {
         // tested at the bottom, so the masks stay in place across steps
-        if (uniform_u64(alive[s0][0]) == 0) continue;
+        if (uniform_u64(cand[s0]) == 0) continue;
         do {
           float row[NA];
           int istar[NA];
+          uint64_t above[NA];
 #pragma unroll
           for (int ai = s0; ai < g1; ++ai) {
-            const uint64_t al = uniform_u64(alive[ai][0]);
-            const int i = ff1_u64(al & vis[ai][0]);
-            // ranks above i; with no candidate (i = -1, shift 63) none, so
-            // every survivor is kept and the chain ends
-            const uint64_t above = 0xFFFFFFFFFFFFFFFEull << (i & 63);
-            const uint64_t k = uniform_u64(kept[ai][0]) | (al & ~above);
-            kept[ai][0] = k;
-            alive[ai][0] = (CAP && __popcll(k) >= rmax[ai]) ? 0ull : al & above;
+            const int i = ff1_u64(uniform_u64(cand[ai]));
+            // ranks after i; with no candidate (i = -1, shift 63) none
+            above[ai] = 0xFFFFFFFFFFFFFFFEull << (i & 63);
             istar[ai] = i & 63;
             row[ai] = St[(i & 63) * 32 + lbase[0]];
           }
@@ -827,9 +831,16 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
           uint64_t any_amb = 0;
 #pragma unroll
           for (int ai = s0; ai < g1; ++ai) {
+            uint64_t ab = above[ai];
+            uint64_t r = uniform_u64(alive[ai][0]);
+            if (CAP && __popcll(r & ~ab) >= rmax[ai]) {  // R kept up to i: stop
+              r &= ~ab;
+              ab = 0;
+            }
             const uint64_t pm = __ballot(row[ai] <= P[0][ai]);
-            amb[ai] = __ballot(row[ai] <= K[0][ai]) & ~pm & alive[ai][0];
-            alive[ai][0] &= ~pm;
+            amb[ai] = __ballot(row[ai] <= K[0][ai]) & ~pm & r & ab;
+            alive[ai][0] = r & ~(pm & ab);
+            above[ai] = ab;
             any_amb |= amb[ai];
           }
           if (uniform_u64(any_amb) != 0) {
@@ -849,9 +860,13 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
               }
             }
           }
-        } while (uniform_u64(alive[s0][0]) != 0);
+#pragma unroll
+          for (int ai = s0; ai < g1; ++ai) cand[ai] = alive[ai][0] & above[ai] & vis[ai][0];
+        } while (uniform_u64(cand[s0]) != 0);
       }
     }
+#pragma unroll
+    for (int ai = 0; ai < NA; ++ai) kept[ai][0] = alive[ai][0];
   } else {
   // Two mask words: each step advances every chain that still has survivors.
   for (;;) {
