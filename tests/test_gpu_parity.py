@@ -11,6 +11,7 @@ import torch
 
 import oracle
 import workloads
+from boundary_cases import boundary_clusters, cluster_graph
 
 pytestmark = pytest.mark.gpu
 
@@ -278,67 +279,15 @@ def test_edge_cases_u8_batched_kernel(d, r_max):
             assert np.array_equal(_np(dg), e_deg), (a, R)
 
 
-def _boundary_clusters(alphas, per_kind=4, seed=11):
-    """Three-point clusters (p, p*, p') with p's list [p*, p'] and S(p, p*) <
-    S(p, p'), per alpha num/den and per kind of the integer test
-    num^2 S(p*, p') <= den^2 S(p, p') of Algorithm 1: equality ("eq"),
-    S(p*, p') = T < den^2 S(p, p') / num^2 ("floor"; none exists for alpha 1),
-    and S(p*, p') = T + 1 ("above"), where T = floor(den^2 S(p, p') / num^2).
-    Offsets are integers in [-40, 40] in four dimensions around byte 128."""
-    rng = np.random.default_rng(seed)
-    found = {}
-    for _ in range(20):
-        v = rng.integers(-40, 41, (200_000, 4))
-        w = rng.integers(-40, 41, (200_000, 4))
-        sv, sw = (v * v).sum(1), (w * w).sum(1)
-        s = ((w - v) ** 2).sum(1)
-        ok = (sv > 0) & (sv < sw)
-        for (num, den) in alphas:
-            lhs, rhs = num * num * s, den * den * sw
-            t = rhs // (num * num)
-            for kind, sel in (("eq", lhs == rhs), ("floor", (lhs != rhs) & (s == t)),
-                              ("above", s == t + 1)):
-                have = found.setdefault(((num, den), kind), [])
-                for i in np.nonzero(ok & sel)[0][: per_kind - len(have)]:
-                    have.append((v[i], w[i]))
-    # equality is rare at random for den^2 / num^2 near 1: take w = (num, 0, 0, 0),
-    # so S(p, p') = num^2, and v on the circle S(p*, p') = den^2 in two dimensions
-    for (num, den) in alphas:
-        have = found[((num, den), "eq")]
-        x, y = np.meshgrid(np.arange(-40, 41), np.arange(-40, 41))
-        on = ((x - num) ** 2 + y ** 2 == den * den) & (x * x + y * y > 0) & (x * x + y * y < num * num)
-        for xi, yi in zip(x[on], y[on]):
-            if len(have) < per_kind:
-                have.append((np.array([xi, yi, 0, 0]), np.array([num, 0, 0, 0])))
-    return found
-
-
 def test_u8_thresholds_at_exact_boundaries():
     """uint8 pairs on the alpha boundary itself and one unit either side of
     the integer threshold, for six alphas in one sweep: the batched kernel's
     thresholds floor(den^2 S(p, p') / num^2) and decision codes must agree with
     the oracle's exact test, which prunes at equality."""
     alphas = [(1, 1), (21, 20), (11, 10), (6, 5), (3, 2), (2, 1)]
-    found = _boundary_clusters(alphas)
+    found = boundary_clusters(alphas)
     assert all(len(c) == 4 for (a, kind), c in found.items() if a != (1, 1) or kind != "floor")
-    d = 16
-    pts, nbr, deg, kinds = [], [], [], []
-    for (a, kind), cases in found.items():
-        for v, w in cases:
-            base = len(pts)
-            p = np.full(d, 128, np.int64)
-            for off in (np.zeros(4, np.int64), v, w):
-                x = p.copy()
-                x[:4] += off
-                pts.append(x)
-            # every other list is out of rank order (the kernel sorts it)
-            first = [base + 1, base + 2] if (base // 3) % 2 == 0 else [base + 2, base + 1]
-            nbr += [first, [-1, -1], [-1, -1]]
-            deg += [2, 0, 0]
-            kinds.append((base, a, kind))
-    X = np.asarray(pts, np.uint8)
-    nbr = np.asarray(nbr, np.int32)
-    deg = np.asarray(deg, np.int32)
+    X, nbr, deg, kinds = cluster_graph(found)
     g = _graph(X, nbr, deg, 0)
     outs = g.prune_sweep(alphas, [2])
     for o, (nb, dg) in enumerate(outs):

@@ -370,3 +370,26 @@ def test_smat_and_points_agree():
             oracle.robust_prune(X, p, cand, 6, 5, 0)
     assert characterises(ExactMatrix(S), 0, [1, 2, 3], 1, 1, 0,
                          oracle.robust_prune_smat(S, 0, [1, 2, 3], 1, 1, 0))
+
+
+def test_uint8_decisions_on_the_alpha_boundary():
+    """Algorithm 1 prunes p' when alpha D(p*, p') <= D(p, p'), i.e. on squared
+    integer distances num^2 S(p*, p') <= den^2 S(p, p'): at equality and at
+    S(p*, p') = T = floor(den^2 S(p, p') / num^2) p' is pruned, one unit above
+    it is kept.  Pairs built on exactly those relations, for six alphas, with
+    lists in and out of rank order; a strict comparison, a rounded threshold or
+    alpha applied to squared distances each flips some of them."""
+    from boundary_cases import boundary_clusters, cluster_graph
+
+    alphas = [(1, 1), (21, 20), (11, 10), (6, 5), (3, 2), (2, 1)]
+    found = boundary_clusters(alphas)
+    assert all(len(c) == 4 for (a, kind), c in found.items() if a != (1, 1) or kind != "floor")
+    X, nbr, deg, kinds = cluster_graph(found)
+    for a in alphas:
+        e_nbr, e_deg, _ = oracle.prune_graph(X, nbr, deg, *a, 2)
+        for base, ca, kind in kinds:
+            if ca != a:
+                continue
+            want = [base + 1, base + 2] if kind == "above" else [base + 1, -1]
+            assert list(e_nbr[base]) == want, (a, kind)
+            assert e_deg[base] == (2 if kind == "above" else 1), (a, kind)
