@@ -55,13 +55,19 @@ def _load():
     lib.rpo_robust_prune.argtypes = [
         C.c_void_p, C.c_int32, C.c_int64, C.c_int32, C.c_int32, _i32p, C.c_int32,
         C.c_int32, C.c_int32, C.c_int32, _i32p, _i64p]
+    lib.rpo_robust_prune_unsorted.restype = C.c_int32
+    lib.rpo_robust_prune_unsorted.argtypes = lib.rpo_robust_prune.argtypes
     lib.rpo_robust_prune_smat.restype = C.c_int32
     lib.rpo_robust_prune_smat.argtypes = [
         _f64p, C.c_int32, C.c_int32, _i32p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _i32p]
+    lib.rpo_robust_prune_unsorted_smat.restype = C.c_int32
+    lib.rpo_robust_prune_unsorted_smat.argtypes = lib.rpo_robust_prune_smat.argtypes
     lib.rpo_prune_graph.restype = C.c_int32
     lib.rpo_prune_graph.argtypes = [
         C.c_void_p, C.c_int32, C.c_int64, C.c_int32, _i32p, _i32p, C.c_int32,
         _i32p, C.c_int64, C.c_int32, C.c_int32, C.c_int32, _i32p, _i32p, _i64p]
+    lib.rpo_prune_graph_unsorted.restype = C.c_int32
+    lib.rpo_prune_graph_unsorted.argtypes = lib.rpo_prune_graph.argtypes
     lib.rpo_search.restype = C.c_int32
     lib.rpo_search.argtypes = [
         C.c_void_p, C.c_int32, C.c_int64, C.c_int32, _i32p, _i32p, C.c_int32,
@@ -105,40 +111,52 @@ def sqdist(a: np.ndarray, b: np.ndarray):
 
 
 def robust_prune(X: np.ndarray, p: int, cand, num: int, den: int, R: int = 0,
-                 count_pairs: bool = False):
-    """RobustPrune(p, cand, alpha=num/den, R) (Algorithm 1).  R <= 0: no bound."""
+                 count_pairs: bool = False, unsorted: bool = False):
+    """RobustPrune(p, cand, alpha=num/den, R) (Algorithm 1).  R <= 0: no bound.
+    unsorted: UnsortedRobustPrune (Section 3), p* = the first remaining
+    candidate in list order."""
     lib = _load()
+    fn = lib.rpo_robust_prune_unsorted if unsorted else lib.rpo_robust_prune
     X = np.ascontiguousarray(X)
     cand = np.ascontiguousarray(np.asarray(cand, dtype=np.int32))
     m = cand.shape[0]
     out = np.full(max(m, 1), -1, dtype=np.int32)
     pairs = np.zeros(1, dtype=np.int64)
-    rc = lib.rpo_robust_prune(X.ctypes.data, _dtype_code(X), X.shape[0], X.shape[1], int(p),
-                              _ptr(cand, _i32p), m, int(num), int(den), int(R),
-                              _ptr(out, _i32p), _ptr(pairs, _i64p))
+    rc = fn(X.ctypes.data, _dtype_code(X), X.shape[0], X.shape[1], int(p),
+            _ptr(cand, _i32p), m, int(num), int(den), int(R),
+            _ptr(out, _i32p), _ptr(pairs, _i64p))
     k = _check(rc, "robust_prune")
     res = [int(v) for v in out[:k]]
     return (res, int(pairs[0])) if count_pairs else res
 
 
-def robust_prune_smat(Smat: np.ndarray, p: int, cand, num: int, den: int, R: int = 0):
-    """RobustPrune on an explicit matrix of squared distances."""
+def robust_prune_smat(Smat: np.ndarray, p: int, cand, num: int, den: int, R: int = 0,
+                      unsorted: bool = False):
+    """RobustPrune (or UnsortedRobustPrune) on an explicit matrix of squared
+    distances."""
     lib = _load()
+    fn = lib.rpo_robust_prune_unsorted_smat if unsorted else lib.rpo_robust_prune_smat
     Smat = np.ascontiguousarray(Smat, dtype=np.float64)
     cand = np.ascontiguousarray(np.asarray(cand, dtype=np.int32))
     m = cand.shape[0]
     out = np.full(max(m, 1), -1, dtype=np.int32)
-    rc = lib.rpo_robust_prune_smat(_ptr(Smat, _f64p), Smat.shape[0], int(p), _ptr(cand, _i32p),
-                                   m, int(num), int(den), int(R), _ptr(out, _i32p))
+    rc = fn(_ptr(Smat, _f64p), Smat.shape[0], int(p), _ptr(cand, _i32p),
+            m, int(num), int(den), int(R), _ptr(out, _i32p))
     k = _check(rc, "robust_prune_smat")
     return [int(v) for v in out[:k]]
 
 
 def prune_graph(X: np.ndarray, nbr: np.ndarray, deg: np.ndarray, num: int, den: int, R: int,
-                nodes=None):
+                nodes=None, unsorted: bool = False, threads: int = 1):
     """RP-Tuning at alpha=num/den with degree bound R over all nodes, or over
-    ``nodes`` only.  Returns (out_nbr [len x R, -1 padded], out_deg, pairs)."""
+    ``nodes`` only.  Returns (out_nbr [len x R, -1 padded], out_deg, pairs).
+    unsorted: UnsortedRobustPrune in place of RobustPrune.  threads > 1 runs
+    the single-threaded oracle on that many disjoint node shards at once (the
+    vertices are independent); the result does not depend on it."""
+    if threads > 1:
+        return _prune_graph_sharded(X, nbr, deg, num, den, R, nodes, unsorted, threads)
     lib = _load()
+    fn = lib.rpo_prune_graph_unsorted if unsorted else lib.rpo_prune_graph
     X = np.ascontiguousarray(X)
     nbr = np.ascontiguousarray(nbr, dtype=np.int32)
     deg = np.ascontiguousarray(deg, dtype=np.int32)
@@ -152,12 +170,32 @@ def prune_graph(X: np.ndarray, nbr: np.ndarray, deg: np.ndarray, num: int, den: 
     out_nbr = np.empty((cnt, R), dtype=np.int32)
     out_deg = np.empty(cnt, dtype=np.int32)
     pairs = np.zeros(1, dtype=np.int64)
-    rc = lib.rpo_prune_graph(X.ctypes.data, _dtype_code(X), X.shape[0], X.shape[1],
-                             _ptr(nbr, _i32p), _ptr(deg, _i32p), nbr.shape[1],
-                             nodes_p, cnt, int(num), int(den), int(R),
-                             _ptr(out_nbr, _i32p), _ptr(out_deg, _i32p), _ptr(pairs, _i64p))
+    rc = fn(X.ctypes.data, _dtype_code(X), X.shape[0], X.shape[1],
+            _ptr(nbr, _i32p), _ptr(deg, _i32p), nbr.shape[1],
+            nodes_p, cnt, int(num), int(den), int(R),
+            _ptr(out_nbr, _i32p), _ptr(out_deg, _i32p), _ptr(pairs, _i64p))
     _check(rc, "prune_graph")
     return out_nbr, out_deg, int(pairs[0])
+
+
+def _prune_graph_sharded(X, nbr, deg, num, den, R, nodes, unsorted, threads):
+    """prune_graph over contiguous shards of the node list, one thread each
+    (ctypes releases the interpreter lock during the call)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    X = np.ascontiguousarray(X)
+    nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+    deg = np.ascontiguousarray(deg, dtype=np.int32)
+    nodes = np.arange(X.shape[0], dtype=np.int32) if nodes is None else \
+        np.ascontiguousarray(np.asarray(nodes, dtype=np.int32))
+    parts = [p for p in np.array_split(nodes, threads) if p.size]
+    with ThreadPoolExecutor(max_workers=len(parts)) as ex:
+        res = list(ex.map(lambda part: prune_graph(X, nbr, deg, num, den, R, nodes=part,
+                                                   unsorted=unsorted), parts))
+    if not res:
+        return np.empty((0, R), np.int32), np.empty(0, np.int32), 0
+    return (np.concatenate([r[0] for r in res]), np.concatenate([r[1] for r in res]),
+            sum(r[2] for r in res))
 
 
 def search(X: np.ndarray, nbr: np.ndarray, deg: np.ndarray, start: int, Q: np.ndarray,

@@ -94,9 +94,14 @@ static int alpha_test(const metric_t* M, int32_t num, int32_t den, double s_star
 /* Algorithm 1: RobustPrune(p, V, alpha, R)                                  */
 /* ------------------------------------------------------------------------ */
 
+/* sorted != 0: RobustPrune, Algorithm 1.  sorted == 0: UnsortedRobustPrune
+ * (Section 3, the paragraph after the RP-Tuning definition): the same
+ * procedure with p* taken as an arbitrary out-neighbour of p instead of the
+ * argmin; "arbitrary" is read as the first candidate still in V in the order
+ * the list stores them. */
 static int32_t robust_prune(const metric_t* M, int32_t p, const int32_t* cand,
                             int32_t m, int32_t num, int32_t den, int32_t R,
-                            int32_t* out, int64_t* pairs) {
+                            int32_t* out, int64_t* pairs, int sorted) {
   if (m < 0 || num < 1 || den < 1 || num < den) return RPO_EINVAL;
   if (m == 0) return 0;
   int32_t* V = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
@@ -131,10 +136,11 @@ static int32_t robust_prune(const metric_t* M, int32_t p, const int32_t* cand,
   int32_t kept = 0;
   int32_t remaining = nv;
   while (remaining > 0) {
-    /* p* <- argmin_{p' in V} D(p, p') */
+    /* p* <- argmin_{p' in V} D(p, p')  (unsorted: the first p' still in V) */
     int32_t best = -1;
     for (int32_t t = 0; t < nv; ++t) {
       if (!inV[t]) continue;
+      if (!sorted) { best = t; break; }
       if (best < 0 || before(Sp[t], V[t], Sp[best], V[best])) best = t;
     }
     /* N_out(p) <- N_out(p) u {p*} */
@@ -169,7 +175,17 @@ int32_t rpo_robust_prune(const void* X, int32_t dt, int64_t n, int32_t d,
   if (!X || (dt != RPO_U8 && dt != RPO_F32) || n < 1 || d < 1) return RPO_EINVAL;
   if (p < 0 || (int64_t)p >= n) return RPO_ERANGE;
   metric_t M = {dt, X, n, d, NULL};
-  return robust_prune(&M, p, cand, m, num, den, R, out, pairs);
+  return robust_prune(&M, p, cand, m, num, den, R, out, pairs, 1);
+}
+
+int32_t rpo_robust_prune_unsorted(const void* X, int32_t dt, int64_t n, int32_t d,
+                                  int32_t p, const int32_t* cand, int32_t m,
+                                  int32_t num, int32_t den, int32_t R,
+                                  int32_t* out, int64_t* pairs) {
+  if (!X || (dt != RPO_U8 && dt != RPO_F32) || n < 1 || d < 1) return RPO_EINVAL;
+  if (p < 0 || (int64_t)p >= n) return RPO_ERANGE;
+  metric_t M = {dt, X, n, d, NULL};
+  return robust_prune(&M, p, cand, m, num, den, R, out, pairs, 0);
 }
 
 int32_t rpo_robust_prune_smat(const double* Smat, int32_t n, int32_t p,
@@ -178,18 +194,27 @@ int32_t rpo_robust_prune_smat(const double* Smat, int32_t n, int32_t p,
   if (!Smat || n < 1) return RPO_EINVAL;
   if (p < 0 || p >= n) return RPO_ERANGE;
   metric_t M = {KIND_SMAT, NULL, n, 0, Smat};
-  return robust_prune(&M, p, cand, m, num, den, R, out, NULL);
+  return robust_prune(&M, p, cand, m, num, den, R, out, NULL, 1);
+}
+
+int32_t rpo_robust_prune_unsorted_smat(const double* Smat, int32_t n, int32_t p,
+                                       const int32_t* cand, int32_t m,
+                                       int32_t num, int32_t den, int32_t R, int32_t* out) {
+  if (!Smat || n < 1) return RPO_EINVAL;
+  if (p < 0 || p >= n) return RPO_ERANGE;
+  metric_t M = {KIND_SMAT, NULL, n, 0, Smat};
+  return robust_prune(&M, p, cand, m, num, den, R, out, NULL, 0);
 }
 
 /* ------------------------------------------------------------------------ */
 /* RP-Tuning: RobustPrune(p, N_out(p), alpha, R) for every p                 */
 /* ------------------------------------------------------------------------ */
 
-int32_t rpo_prune_graph(const void* X, int32_t dt, int64_t n, int32_t d,
-                        const int32_t* nbr, const int32_t* deg, int32_t stride,
-                        const int32_t* nodes, int64_t n_nodes,
-                        int32_t num, int32_t den, int32_t R,
-                        int32_t* out_nbr, int32_t* out_deg, int64_t* pairs) {
+static int32_t prune_graph(const void* X, int32_t dt, int64_t n, int32_t d,
+                           const int32_t* nbr, const int32_t* deg, int32_t stride,
+                           const int32_t* nodes, int64_t n_nodes,
+                           int32_t num, int32_t den, int32_t R,
+                           int32_t* out_nbr, int32_t* out_deg, int64_t* pairs, int sorted) {
   if (!X || !nbr || !deg || !out_nbr || !out_deg) return RPO_EINVAL;
   if ((dt != RPO_U8 && dt != RPO_F32) || n < 1 || d < 1 || stride < 1 || R < 1)
     return RPO_EINVAL;
@@ -202,13 +227,32 @@ int32_t rpo_prune_graph(const void* X, int32_t dt, int64_t n, int32_t d,
     if (p < 0 || p >= n) { free(tmp); return RPO_ERANGE; }
     int32_t m = deg[p];
     if (m < 0 || m > stride) { free(tmp); return RPO_EINVAL; }
-    int32_t k = robust_prune(&M, (int32_t)p, nbr + p * stride, m, num, den, R, tmp, pairs);
+    int32_t k = robust_prune(&M, (int32_t)p, nbr + p * stride, m, num, den, R, tmp, pairs,
+                             sorted);
     if (k < 0) { free(tmp); return k; }
     for (int32_t u = 0; u < R; ++u) out_nbr[t * R + u] = u < k ? tmp[u] : -1;
     out_deg[t] = k;
   }
   free(tmp);
   return 0;
+}
+
+int32_t rpo_prune_graph(const void* X, int32_t dt, int64_t n, int32_t d,
+                        const int32_t* nbr, const int32_t* deg, int32_t stride,
+                        const int32_t* nodes, int64_t n_nodes,
+                        int32_t num, int32_t den, int32_t R,
+                        int32_t* out_nbr, int32_t* out_deg, int64_t* pairs) {
+  return prune_graph(X, dt, n, d, nbr, deg, stride, nodes, n_nodes, num, den, R, out_nbr,
+                     out_deg, pairs, 1);
+}
+
+int32_t rpo_prune_graph_unsorted(const void* X, int32_t dt, int64_t n, int32_t d,
+                                 const int32_t* nbr, const int32_t* deg, int32_t stride,
+                                 const int32_t* nodes, int64_t n_nodes,
+                                 int32_t num, int32_t den, int32_t R,
+                                 int32_t* out_nbr, int32_t* out_deg, int64_t* pairs) {
+  return prune_graph(X, dt, n, d, nbr, deg, stride, nodes, n_nodes, num, den, R, out_nbr,
+                     out_deg, pairs, 0);
 }
 
 /* ------------------------------------------------------------------------ */

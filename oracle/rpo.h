@@ -71,6 +71,21 @@ int32_t rpo_robust_prune_smat(const double* Smat, int32_t n, int32_t p,
                               int32_t num, int32_t den, int32_t R, int32_t* out);
 
 /*
+ * UnsortedRobustPrune (Section 3, defined right after RP-Tuning): Algorithm 1
+ * with p* taken as an arbitrary remaining out-neighbour of p instead of the
+ * argmin.  Read here as the first id of V still present, in the order the
+ * list stores them (V keeps the first occurrence of a repeated id).  Same
+ * arguments and outputs as rpo_robust_prune / rpo_robust_prune_smat.
+ */
+int32_t rpo_robust_prune_unsorted(const void* X, int32_t dt, int64_t n, int32_t d,
+                                  int32_t p, const int32_t* cand, int32_t m,
+                                  int32_t num, int32_t den, int32_t R,
+                                  int32_t* out, int64_t* pairs);
+int32_t rpo_robust_prune_unsorted_smat(const double* Smat, int32_t n, int32_t p,
+                                       const int32_t* cand, int32_t m,
+                                       int32_t num, int32_t den, int32_t R, int32_t* out);
+
+/*
  * RP-Tuning (Section 3): RobustPrune(p, N_out(p), alpha, R) for every node p
  * listed in nodes[0..n_nodes) (nodes == NULL means all n nodes in order).
  * Adjacency: nbr is n x stride int32 (row p holds deg[p] ids, rest ignored).
@@ -82,6 +97,14 @@ int32_t rpo_prune_graph(const void* X, int32_t dt, int64_t n, int32_t d,
                         const int32_t* nodes, int64_t n_nodes,
                         int32_t num, int32_t den, int32_t R,
                         int32_t* out_nbr, int32_t* out_deg, int64_t* pairs);
+
+/* RP-Tuning with UnsortedRobustPrune in place of RobustPrune (Theorem 3.1's
+ * setting); same arguments as rpo_prune_graph. */
+int32_t rpo_prune_graph_unsorted(const void* X, int32_t dt, int64_t n, int32_t d,
+                                 const int32_t* nbr, const int32_t* deg, int32_t stride,
+                                 const int32_t* nodes, int64_t n_nodes,
+                                 int32_t num, int32_t den, int32_t R,
+                                 int32_t* out_nbr, int32_t* out_deg, int64_t* pairs);
 
 /*
  * GreedySearch(s, q, k, L), Algorithm 2, for nq queries (nq x d, same dtype
