@@ -81,8 +81,10 @@ typedef struct {
  *   start  : start vertex s of GreedySearch (Algorithm 2), 0 <= start < n.
  * The library BORROWS points, nbr and deg until rp_free_graph: they must stay
  * valid and unmodified.  The adjacency is validated on the device; this call
- * synchronises `stream` and returns RP_ERANGE if any degree is outside
- * [0, r_max] or any listed id outside [0, n).  On success *out receives a new
+ * is synchronous (it returns once everything it enqueued on `stream` is done,
+ * so the handle may be used from any stream) and returns RP_ERANGE if any
+ * degree is outside [0, r_max] or any listed id outside [0, n), RP_EINVAL if
+ * a float32 point has a NaN or infinite coordinate.  On success *out receives a new
  * handle.  The handle owns one device array per point (|x|^2 for uint8 points,
  * max_k |x_k| for float32 ones) and, for float32 graphs with r_max <= 96, one
  * byte per vertex: the scale exponent of the vertex's frame, computed from
@@ -96,8 +98,10 @@ rp_status rp_load_graph(const void* points, int32_t dtype, int64_t n, int32_t d,
  * rp_graph_derive -- a handle on another graph over the same points (for
  * example a pruned graph, to search it).  Shares base's points and start
  * vertex; borrows nbr/deg like rp_load_graph and validates them the same way
- * (synchronous), and computes its own per-vertex frame exponents for float32
- * graphs with r_max <= 96 (n bytes).  base must outlive the derived handle.
+ * (synchronous, as rp_load_graph), and computes its own per-vertex frame
+ * exponents for float32 graphs that the batched kernel serves (r_max <= 96,
+ * and r_max <= 64 above d = 3408; n bytes).  base must outlive the derived
+ * handle.
  */
 rp_status rp_graph_derive(rp_graph_t base, const int32_t* nbr, const int32_t* deg,
                           int32_t r_max, void* stream, rp_graph_t* out);
@@ -126,6 +130,19 @@ rp_status rp_prune(rp_graph_t g, rp_alpha alpha, int32_t R, int32_t* out_nbr,
 rp_status rp_prune_sweep(rp_graph_t g, const rp_alpha* alphas, int32_t n_a,
                          const int32_t* Rs, int32_t n_R, int32_t* const* out_nbr,
                          int32_t* const* out_deg, void* stream);
+
+/*
+ * rp_prune_sweep_unsorted -- RP-Tuning with UnsortedRobustPrune (Section 3,
+ * defined after RP-Tuning; the setting of Theorem 3.1): Algorithm 1 with p*
+ * taken as an arbitrary remaining out-neighbour of p instead of the argmin
+ * of D(p, .).  "Arbitrary" is read as the first remaining candidate in the
+ * order the list stores them (a repeated id counts at its first occurrence;
+ * p itself is dropped).  Arguments, output layout and errors as
+ * rp_prune_sweep; each output row holds the kept ids in that list order.
+ */
+rp_status rp_prune_sweep_unsorted(rp_graph_t g, const rp_alpha* alphas, int32_t n_a,
+                                  const int32_t* Rs, int32_t n_R, int32_t* const* out_nbr,
+                                  int32_t* const* out_deg, void* stream);
 
 /*
  * rp_prune_plain -- the same result as rp_prune from the plain baseline

@@ -39,7 +39,10 @@
  * computes each vertex and each query independently).
  *
  * All pointers in rp_request are DEVICE pointers owned by the caller and must
- * stay valid until the request completes.  Calls are thread-safe.
+ * stay valid until the request completes.  The server's streams are not
+ * ordered after the caller's: a request's input rows must be complete when it
+ * is submitted (synchronise the stream that produced them first).  Calls are
+ * thread-safe.
  */
 #ifndef RP_SERVE_H
 #define RP_SERVE_H

@@ -177,12 +177,15 @@ __device__ __forceinline__ void wave_sync() {
 
 // Power-of-two scale of a float32 vertex frame: |x_jk - x_pk| <= bound <
 // 2^ex, e = 14 - ex, so every scaled difference is below 2^14 in magnitude.
-__device__ __forceinline__ int frame_exponent(float bound) {
+// The bound is a sum of two finite floats taken in FP64 (below 2^129), so
+// ex <= 129 and e >= -115: 2^e stays a normal float.  The cap at 100 only
+// shrinks the scaled values further.
+__device__ __forceinline__ int frame_exponent(double bound) {
   int e = 0;
-  if (bound > 0.f) {
+  if (bound > 0.0) {
     int ex;
-    frexpf(bound, &ex);
-    e = min(100, max(-100, 14 - ex));
+    frexp(bound, &ex);
+    e = min(100, max(-115, 14 - ex));
   }
   return e;
 }

@@ -60,7 +60,7 @@ hipError_t launch_prune_batched(const GraphView& g, const SweepArgs& a, DevCount
   for (int o = 0; o < a.n_out; ++o) {
     const SweepOut& out = a.out[o];
     hipError_t e = launch_prune_plain(g, a.num2[out.alpha_idx], a.den2[out.alpha_idx], out.R,
-                                      out.nbr, out.deg, ctr, s);
+                                      out.nbr, out.deg, ctr, s, a.unsorted != 0);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

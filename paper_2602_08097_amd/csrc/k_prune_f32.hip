@@ -19,7 +19,8 @@
 //              S(p, t): t = (double)a - (double)b, fused multiply-add, k
 //              ascending.
 //  a4  sort:   (S(p, j), id) ascending -- the order in which the repeated
-//              argmin of Algorithm 1 visits the candidates.  A list already in
+//              argmin of Algorithm 1 visits the candidates (UnsortedRobustPrune,
+//              Section 3, keeps the list order instead).  A list already in
 //              that order (every RobustPrune output is) is used as read;
 //              otherwise the keys are sorted and the rows are streamed a
 //              second time in rank order.  Repeated ids are dropped.
@@ -585,7 +586,7 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
       const uint32_t ll = (uint32_t)__shfl((int)kl[0], 63, 64);
       unsorted = unsorted || (lane == 0 && key_less(kh[NW - 1], kl[NW - 1], lh, ll));
     }
-    if (__ballot(unsorted) != 0) {
+    if (!a.unsorted && __ballot(unsorted) != 0) {
       // out of rank order: sort the keys, stream the rows again by rank
       if constexpr (NW == 2) wave_sort128(kh[0], kl[0], kh[1], kl[1], lane);
       else wave_sort2(kh[0], kl[0], lane);
@@ -617,6 +618,27 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
   uint64_t vm[NW];
   int id_rank[NW];
   double sw[NW], s2[NW];
+  // UnsortedRobustPrune (Section 3): the ranks are the list order, and a
+  // repeated id counts at its first slot
+  bool later[NW];
+#pragma unroll
+  for (int w = 0; w < NW; ++w) later[w] = false;
+  if (a.unsorted) {
+#pragma unroll 1
+    for (int t = 0; t < 64; ++t) {
+      const int v = __builtin_amdgcn_readlane(idw[0], t);
+#pragma unroll
+      for (int w = 0; w < NW; ++w)
+        later[w] = later[w] || (t < lane + 64 * w && v >= 0 && v == idw[w]);
+    }
+    if constexpr (NW == 2) {
+#pragma unroll 1
+      for (int t = 0; t < 32; ++t) {
+        const int v = __builtin_amdgcn_readlane(idw[1], t);
+        later[1] = later[1] || (t < lane && v >= 0 && v == idw[1]);
+      }
+    }
+  }
   {
     const uint64_t last0h = shfl_u64(kh[0], 63);
     const uint32_t last0l = (uint32_t)__shfl((int)kl[0], 63, 64);
@@ -629,7 +651,8 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
         ph = w == 0 ? ~0ull - 1 : last0h;
         pl = w == 0 ? 0u : last0l;
       }
-      valid[w] = kh[w] != ~0ull && !(kh[w] == ph && (kl[w] >> SB) == (pl >> SB));
+      valid[w] = kh[w] != ~0ull &&
+                 (a.unsorted ? !later[w] : !(kh[w] == ph && (kl[w] >> SB) == (pl >> SB)));
       vm[w] = __ballot(valid[w]);
       id_rank[w] = valid[w] ? (int)(kl[w] >> SB) : -1;
       sw[w] = valid[w] ? __longlong_as_double((long long)kh[w]) : 0.0;
@@ -1221,9 +1244,15 @@ SweepArgs alphas_descending(const SweepArgs& a_in, int nr) {
 
 int prune_f32_wave_lds(const GraphView& g) { return plan_of(g).wave_lds; }
 
-bool prune_f32_supported(const GraphView& g) {
+// Lists of at most 96 ids whose per-wavefront LDS fits a workgroup (96
+// candidates above d = 3408 do not: those graphs take the plain kernel).
+bool prune_f32_shape_ok(const GraphView& g) {
   return g.dtype == RP_F32 && g.r_max <= 96 && g.d <= kMaxDimF32 && g.n <= (1ll << 25) &&
-         g.maxabs != nullptr;
+         g.maxabs != nullptr && plan_of(g).wave_lds <= kMaxLdsPerGroup;
+}
+
+bool prune_f32_supported(const GraphView& g) {
+  return prune_f32_shape_ok(g) && g.frame_e != nullptr;
 }
 
 hipError_t launch_gram_error_f32(const GraphView& g, const int32_t* nodes, int64_t n_nodes,

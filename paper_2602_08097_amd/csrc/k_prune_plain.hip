@@ -5,7 +5,8 @@
 // ids are dropped, D(p, .) is computed once per candidate, the candidates are
 // ranked by (S(p, .), id) (the repeated argmin of Algorithm 1 over a set that
 // only loses members visits them in this order), and the greedy loop walks
-// that order: each survivor p* is kept, the loop stops at the R-th keep, and
+// that order (UnsortedRobustPrune, Section 3: the stored list order instead):
+// each survivor p* is kept, the loop stops at the R-th keep, and
 // the lanes evaluate alpha * D(p*, p') <= D(p, p') for every later survivor,
 // computing D(p*, p') on demand from the rows in global memory.
 //   uint8  : exact int32 distances, exact integer test.
@@ -20,7 +21,8 @@ __global__ __launch_bounds__(64) void prune_plain_kernel(GraphView g, uint32_t n
                                                          uint32_t den2, int32_t R,
                                                          int32_t* __restrict__ out_nbr,
                                                          int32_t* __restrict__ out_deg,
-                                                         double rel, DevCounters* ctr) {
+                                                         double rel, DevCounters* ctr,
+                                                         bool unsorted) {
   __shared__ int32_t ids[kMaxRmax];
   __shared__ double sp[kMaxRmax];      // S(p, candidate)
   __shared__ int16_t order[kMaxRmax];  // rank -> candidate slot
@@ -57,12 +59,12 @@ __global__ __launch_bounds__(64) void prune_plain_kernel(GraphView g, uint32_t n
   }
   __syncthreads();
 
-  // Rank by (S(p, .), id).
+  // Rank by (S(p, .), id); UnsortedRobustPrune keeps the list order.
   for (int t = lane; t < m; t += kWave) {
     if (!valid[t]) continue;
     int r = 0;
     for (int u = 0; u < m; ++u)
-      if (valid[u] && before_f64(sp[u], ids[u], sp[t], ids[t])) ++r;
+      if (valid[u] && (unsorted ? u < t : before_f64(sp[u], ids[u], sp[t], ids[t]))) ++r;
     order[r] = (int16_t)t;
   }
   const int nv = s_nvalid;
@@ -114,15 +116,15 @@ __global__ __launch_bounds__(64) void prune_plain_kernel(GraphView g, uint32_t n
 
 hipError_t launch_prune_plain(const GraphView& g, uint32_t num2, uint32_t den2, int32_t R,
                               int32_t* out_nbr, int32_t* out_deg, DevCounters* ctr,
-                              hipStream_t s) {
+                              hipStream_t s, bool unsorted) {
   const double rel = f32_rel_bound(g.d);
   dim3 grid((unsigned)g.n), block(kWave);
   if (g.dtype == RP_U8)
     hipLaunchKernelGGL(prune_plain_kernel<RP_U8>, grid, block, 0, s, g, num2, den2, R, out_nbr,
-                       out_deg, rel, ctr);
+                       out_deg, rel, ctr, unsorted);
   else
     hipLaunchKernelGGL(prune_plain_kernel<RP_F32>, grid, block, 0, s, g, num2, den2, R, out_nbr,
-                       out_deg, rel, ctr);
+                       out_deg, rel, ctr, unsorted);
   return hipGetLastError();
 }
 

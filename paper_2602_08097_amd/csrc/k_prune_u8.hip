@@ -17,7 +17,8 @@
 //              two halves of a row combined across lanes l and l + 32),
 //              <u_p, u_j> and |u_p|^2 on the matrix unit with x_p in every row
 //              of the left operand.
-//  a4  sort:   keys (S(p, j), id, slot) packed in 64 bits.  A list already in
+//  a4  sort:   keys (S(p, j), id, slot) packed in 64 bits (UnsortedRobustPrune,
+//              Section 3, keeps the list order and skips this step).  A list already in
 //              (S, id) order -- every RobustPrune output is -- keeps its rows
 //              where they are; otherwise a 64-lane bitonic sort (DPP and
 //              swizzle exchanges) orders the keys and the rows move to their
@@ -271,29 +272,38 @@ __device__ __forceinline__ Front node_front(uint8_t* C, int32_t* nr, const Graph
   uint64_t key = usable >= 0
                      ? (((uint64_t)sp << shift) | ((uint64_t)(uint32_t)id << 6) | (uint64_t)lane)
                      : kInvalid;
-  uint64_t prev = shfl_u64(key, lane > 0 ? lane - 1 : 0);
-  if (__ballot(lane > 0 && key < prev)) {
-    key = wave_sort(key, lane);
-    prev = shfl_u64(key, lane > 0 ? lane - 1 : 0);
-    // rows to their ranks: row of rank 32 b + l32 comes from slot sl_b,
-    // held by lane (sl_b % 32) + 32 half of block sl_b / 32
-    const int slot = (int)(key & 63);
-    const int sl0 = __shfl(slot, l32, 64);
-    const int sl1 = __shfl(slot, 32 + l32, 64);
-    const int src0 = (sl0 & 31) + 32 * half;
-    const int src1 = (sl1 & 31) + 32 * half;
-#pragma unroll
-    for (int k = 0; k < NK; ++k) {
-      const v4i a0 = shfl_v4i(f0[k], src0), b0 = shfl_v4i(f1[k], src0);
-      const v4i a1 = shfl_v4i(f0[k], src1), b1 = shfl_v4i(f1[k], src1);
-      f0[k] = sl0 >= 32 ? b0 : a0;
-      f1[k] = sl1 >= 32 ? b1 : a1;
+  bool dup = false;
+  if (a.unsorted) {
+    // UnsortedRobustPrune: the ranks are the list order (no sort); a repeated
+    // id counts at its first slot
+#pragma unroll 1
+    for (int t = 0; t < 63; ++t) {
+      const int v = __builtin_amdgcn_readlane(usable, t);
+      dup = dup || (t < lane && v >= 0 && v == usable);
     }
+  } else {
+    uint64_t prev = shfl_u64(key, lane > 0 ? lane - 1 : 0);
+    if (__ballot(lane > 0 && key < prev)) {
+      key = wave_sort(key, lane);
+      prev = shfl_u64(key, lane > 0 ? lane - 1 : 0);
+      // rows to their ranks: row of rank 32 b + l32 comes from slot sl_b,
+      // held by lane (sl_b % 32) + 32 half of block sl_b / 32
+      const int slot = (int)(key & 63);
+      const int sl0 = __shfl(slot, l32, 64);
+      const int sl1 = __shfl(slot, 32 + l32, 64);
+      const int src0 = (sl0 & 31) + 32 * half;
+      const int src1 = (sl1 & 31) + 32 * half;
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        const v4i a0 = shfl_v4i(f0[k], src0), b0 = shfl_v4i(f1[k], src0);
+        const v4i a1 = shfl_v4i(f0[k], src1), b1 = shfl_v4i(f1[k], src1);
+        f0[k] = sl0 >= 32 ? b0 : a0;
+        f1[k] = sl1 >= 32 ? b1 : a1;
+      }
+    }
+    dup = lane > 0 && key != kInvalid && (key >> 6) == (prev >> 6);
   }
-  {
-    const bool dup = lane > 0 && key != kInvalid && (key >> 6) == (prev >> 6);
-    if (dup) key = kInvalid - 1;  // never alive
-  }
+  if (dup) key = kInvalid - 1;  // never alive
   const bool valid = key < kInvalid - 1;
   Front f;
   f.valid_mask = __ballot(valid);

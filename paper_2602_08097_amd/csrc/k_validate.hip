@@ -43,22 +43,32 @@ hipError_t launch_norms_u8(const GraphView& g, uint32_t* norms, hipStream_t s) {
   return hipGetLastError();
 }
 
-// max_k |x_k| of every float32 point, for the MFMA scale of a vertex's frame.
+// max_k |x_k| of every float32 point, for the MFMA scale of a vertex's frame;
+// points with a NaN or infinite coordinate are counted into ctr->errors (the
+// distances of Section 4 are defined on finite coordinates only).
 __global__ void maxabs_f32_kernel(const float* __restrict__ X, int64_t n, int d,
-                                  float* __restrict__ maxabs) {
+                                  float* __restrict__ maxabs, DevCounters* ctr) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  const float* x = X + p * d;
-  float acc = 0.f;
-  for (int k = 0; k < d; ++k) acc = fmaxf(acc, fabsf(x[k]));
-  maxabs[p] = acc;
+  bool bad = false;
+  if (p < n) {
+    const float* x = X + p * d;
+    float acc = 0.f;
+    for (int k = 0; k < d; ++k) {
+      const float a = fabsf(x[k]);
+      bad = bad || !(a <= 3.40282347e38f);  // NaN or infinity
+      acc = fmaxf(acc, a);
+    }
+    maxabs[p] = acc;
+  }
+  unsigned long long cnt = __popcll(__ballot(bad));
+  if ((threadIdx.x & (kWave - 1)) == 0 && cnt) atomicAdd(&ctr->errors, cnt);
 }
 
-hipError_t launch_maxabs_f32(const GraphView& g, float* maxabs, hipStream_t s) {
+hipError_t launch_maxabs_f32(const GraphView& g, float* maxabs, DevCounters* ctr, hipStream_t s) {
   const int block = 256;
   const int64_t grid = (g.n + block - 1) / block;
   hipLaunchKernelGGL(maxabs_f32_kernel, dim3((unsigned)grid), dim3(block), 0, s,
-                     (const float*)g.X, g.n, g.d, maxabs);
+                     (const float*)g.X, g.n, g.d, maxabs, ctr);
   return hipGetLastError();
 }
 
@@ -75,7 +85,8 @@ __global__ void frame_exponents_f32_kernel(GraphView g, int8_t* __restrict__ e) 
     if (id >= 0 && id != (int)p) mj = fmaxf(mj, g.maxabs[id]);
   }
   for (int off = 32; off > 0; off >>= 1) mj = fmaxf(mj, __shfl_xor(mj, off, 64));
-  if (lane == 0) e[p] = (int8_t)frame_exponent(mj + g.maxabs[p]);
+  // the bound in FP64: the sum of two finite floats stays finite
+  if (lane == 0) e[p] = (int8_t)frame_exponent((double)mj + (double)g.maxabs[p]);
 }
 
 hipError_t launch_frame_exponents_f32(const GraphView& g, int8_t* e, hipStream_t s) {

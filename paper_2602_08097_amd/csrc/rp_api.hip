@@ -98,12 +98,29 @@ rp_status validate_adjacency(const rp::GraphView& v, rp::DevCounters* ctr, hipSt
   return RP_OK;
 }
 
+// The per-point max |x_k| of a float32 point set; a point with a NaN or
+// infinite coordinate makes the load fail (synchronous: reads the count back).
+rp_status add_maxabs(rp_graph* g, hipStream_t s) {
+  rp_status st =
+      check_launch(rp::launch_maxabs_f32(g->view, (float*)g->aux, g->ctr, s), "maxabs");
+  if (st != RP_OK) return st;
+  rp::DevCounters host = {}, zero = {};
+  hipError_t e = hipMemcpyAsync(&host, g->ctr, sizeof(host), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(g->ctr, &zero, sizeof(zero), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return check_launch(e, "maxabs readback");
+  if (host.errors)
+    return fail(RP_EINVAL, "%llu points have a NaN or infinite coordinate",
+                (unsigned long long)host.errors);
+  return RP_OK;
+}
+
 // Float32 graphs that the batched prune serves (lists of at most 96 ids) get
 // the frame exponent of every vertex once, so a sweep reads one byte per
 // vertex instead of max|x| of every candidate.
 rp_status add_frame_exponents(rp_graph* g, hipStream_t stream) {
   g->frame_e = nullptr;
-  if (g->view.dtype != RP_F32 || !rp::prune_f32_supported(g->view)) return RP_OK;
+  if (g->view.dtype != RP_F32 || !rp::prune_f32_shape_ok(g->view)) return RP_OK;
   if (hipMalloc(&g->frame_e, (size_t)g->view.n) != hipSuccess) {
     (void)hipGetLastError();
     g->frame_e = nullptr;
@@ -174,11 +191,13 @@ rp_status rp_load_graph(const void* points, int32_t dtype, int64_t n, int32_t d,
                         "norms");
     } else {
       g->view.maxabs = (const float*)g->aux;
-      st = check_launch(rp::launch_maxabs_f32(g->view, (float*)g->aux, (hipStream_t)stream),
-                        "maxabs");
+      st = add_maxabs(g, (hipStream_t)stream);
       if (st == RP_OK) st = add_frame_exponents(g, (hipStream_t)stream);
     }
   }
+  // the per-point arrays are complete when the call returns, so work on any
+  // other stream (a server's) may read them
+  if (st == RP_OK) st = check_launch(hipStreamSynchronize((hipStream_t)stream), "load sync");
   if (st != RP_OK) {
     if (g->frame_e) (void)hipFree(g->frame_e);
     if (g->aux) (void)hipFree(g->aux);
@@ -215,6 +234,7 @@ rp_status rp_graph_derive(rp_graph_t base, const int32_t* nbr, const int32_t* de
   g->frame_e = nullptr;
   rp_status st = validate_adjacency(g->view, g->ctr, (hipStream_t)stream);
   if (st == RP_OK) st = add_frame_exponents(g, (hipStream_t)stream);
+  if (st == RP_OK) st = check_launch(hipStreamSynchronize((hipStream_t)stream), "derive sync");
   if (st != RP_OK) {
     if (g->frame_e) (void)hipFree(g->frame_e);
     (void)hipFree(g->ctr);
@@ -252,7 +272,7 @@ namespace {
 
 rp_status sweep_args(rp_graph_t g, const rp_alpha* alphas, int32_t n_a, const int32_t* Rs,
                      int32_t n_R, int32_t* const* out_nbr, int32_t* const* out_deg,
-                     rp::SweepArgs* a_out) {
+                     rp::SweepArgs* a_out, bool unsorted = false) {
   if (!g) return fail(RP_ESTATE, "graph is null");
   if (!alphas || !Rs || !out_nbr || !out_deg) return fail(RP_EINVAL, "null host array");
   if (n_a < 1 || n_a > rp::kMaxAlphas)
@@ -261,6 +281,7 @@ rp_status sweep_args(rp_graph_t g, const rp_alpha* alphas, int32_t n_a, const in
   rp::SweepArgs a = {};
   a.n_alpha = n_a;
   a.n_out = n_a * n_R;
+  a.unsorted = unsorted ? 1 : 0;
   for (int i = 0; i < n_a; ++i) {
     rp_status st = check_alpha(alphas[i]);
     if (st != RP_OK) return st;
@@ -451,6 +472,19 @@ rp_status rp_prune_sweep(rp_graph_t g, const rp_alpha* alphas, int32_t n_a, cons
                          void* stream) {
   rp::SweepArgs a;
   rp_status st0 = sweep_args(g, alphas, n_a, Rs, n_R, out_nbr, out_deg, &a);
+  if (st0 != RP_OK) return st0;
+  rp_status st = check_launch(rp::launch_prune_batched(g->view, a, g->ctr, (hipStream_t)stream),
+                              "prune_batched");
+  if (st != RP_OK) return st;
+  g->nodes += g->view.n * a.n_out;
+  return ok();
+}
+
+rp_status rp_prune_sweep_unsorted(rp_graph_t g, const rp_alpha* alphas, int32_t n_a,
+                                  const int32_t* Rs, int32_t n_R, int32_t* const* out_nbr,
+                                  int32_t* const* out_deg, void* stream) {
+  rp::SweepArgs a;
+  rp_status st0 = sweep_args(g, alphas, n_a, Rs, n_R, out_nbr, out_deg, &a, true);
   if (st0 != RP_OK) return st0;
   rp_status st = check_launch(rp::launch_prune_batched(g->view, a, g->ctr, (hipStream_t)stream),
                               "prune_batched");

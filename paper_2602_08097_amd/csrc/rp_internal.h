@@ -41,6 +41,10 @@ struct SweepArgs {
   uint64_t thr_mul[kMaxAlphas];
   int32_t n_alpha;
   int32_t n_out;
+  // 0: RobustPrune (candidates in ascending (S(p, .), id) order); 1:
+  // UnsortedRobustPrune (candidates in stored list order, first occurrence of
+  // a repeated id)
+  int32_t unsorted;
   SweepOut out[kMaxOutputs];
 };
 
@@ -80,16 +84,17 @@ struct SearchJob {
 // Kernel launchers (each returns hipGetLastError() of its launch).
 hipError_t launch_validate(const GraphView& g, DevCounters* ctr, hipStream_t s);
 hipError_t launch_norms_u8(const GraphView& g, uint32_t* norms, hipStream_t s);
-hipError_t launch_maxabs_f32(const GraphView& g, float* maxabs, hipStream_t s);
+hipError_t launch_maxabs_f32(const GraphView& g, float* maxabs, DevCounters* ctr, hipStream_t s);
 hipError_t launch_frame_exponents_f32(const GraphView& g, int8_t* e, hipStream_t s);
 hipError_t launch_prune_plain(const GraphView& g, uint32_t num2, uint32_t den2, int32_t R,
                               int32_t* out_nbr, int32_t* out_deg, DevCounters* ctr,
-                              hipStream_t s);
+                              hipStream_t s, bool unsorted = false);
 hipError_t launch_prune_batched(const GraphView& g, const SweepArgs& a, DevCounters* ctr,
                                 hipStream_t s);
 hipError_t launch_gram_error_f32(const GraphView& g, const int32_t* nodes, int64_t n_nodes,
                                  GramErrorStats* stats, DevCounters* ctr, hipStream_t s);
-bool prune_f32_supported(const GraphView& g);
+bool prune_f32_shape_ok(const GraphView& g);   // shape the float32 batched kernel serves
+bool prune_f32_supported(const GraphView& g);  // ... and its frame exponents are set
 hipError_t launch_search(const GraphView& g, const void* Q, int64_t nq, int32_t k, int32_t L,
                          int32_t* out_ids, double* out_dist, int32_t* out_hops,
                          hipStream_t s);

@@ -58,6 +58,7 @@ REQ_PRUNE = 1
 REQ_QUERY = 2
 
 EXPORTS = ["rp_load_graph", "rp_graph_derive", "rp_prune", "rp_prune_sweep", "rp_prune_plain",
+           "rp_prune_sweep_unsorted",
            "rp_search", "rp_read_counters", "rp_free_graph", "rp_last_error",
            "rp_plan_sweep", "rp_plan_launch", "rp_plan_free",
            "rp_autotune_sweep", "rp_tune_set", "rp_tune_get", "rp_gram_error",
@@ -87,6 +88,8 @@ def load_library(path: str = LIB_PATH):
     lib.rp_prune_sweep.restype = i32
     lib.rp_prune_sweep.argtypes = [vp, C.POINTER(Alpha), i32, C.POINTER(i32), i32,
                                    C.POINTER(vp), C.POINTER(vp), vp]
+    lib.rp_prune_sweep_unsorted.restype = i32
+    lib.rp_prune_sweep_unsorted.argtypes = lib.rp_prune_sweep.argtypes
     lib.rp_search.restype = i32
     lib.rp_search.argtypes = [vp, vp, i64, i32, i32, vp, vp, vp, vp]
     lib.rp_read_counters.restype = i32
@@ -219,8 +222,10 @@ class Graph:
                                    dg.data_ptr(), _stream_ptr(stream)))
         return nb, dg
 
-    def prune_sweep(self, alphas: Sequence, Rs: Sequence[int], outs=None, stream=None):
-        """Returns a list of (nbr, deg) in order o = ia * len(Rs) + iR."""
+    def prune_sweep(self, alphas: Sequence, Rs: Sequence[int], outs=None, stream=None,
+                    unsorted: bool = False):
+        """Returns a list of (nbr, deg) in order o = ia * len(Rs) + iR.
+        unsorted: UnsortedRobustPrune (rp_prune_sweep_unsorted)."""
         al = [as_alpha(a) for a in alphas]
         na, nr = len(al), len(Rs)
         if outs is None:
@@ -231,7 +236,8 @@ class Graph:
         RR = (C.c_int32 * nr)(*[int(r) for r in Rs])
         NB = (C.c_void_p * (na * nr))(*[o[0].data_ptr() for o in outs])
         DG = (C.c_void_p * (na * nr))(*[o[1].data_ptr() for o in outs])
-        _check(_lib.rp_prune_sweep(self.handle, A, na, RR, nr, NB, DG, _stream_ptr(stream)))
+        fn = _lib.rp_prune_sweep_unsorted if unsorted else _lib.rp_prune_sweep
+        _check(fn(self.handle, A, na, RR, nr, NB, DG, _stream_ptr(stream)))
         return outs
 
     def plan_sweep(self, alphas: Sequence, Rs: Sequence[int], outs=None, stream=None) -> "Plan":

@@ -15,6 +15,8 @@ import workloads
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
+THREADS = 8  # the oracle runs single-threaded on this many disjoint vertex shards at once
+
 
 def _dev():
     if not torch.cuda.is_available():
@@ -50,7 +52,7 @@ class Full:
         # the oracle's base rows for the sample, from the same K-NN lists
         _say(f"oracle base rows for {self.nodes.size} vertices")
         o_nbr, o_deg, _ = oracle.prune_graph(w.X, w.knn, w.knn_deg, *self.spec.base_alpha,
-                                             self.spec.base_R, nodes=self.nodes)
+                                             self.spec.base_R, nodes=self.nodes, threads=THREADS)
         g_nbr, g_deg = _np(nb)[self.nodes], _np(dg)[self.nodes]
         assert np.array_equal(g_deg, o_deg), "base degrees differ on the sample"
         assert np.array_equal(g_nbr, o_nbr), "base rows differ on the sample"
@@ -77,7 +79,8 @@ def _check_sampled(f, outs):
     nr = len(f.spec.Rs)
     for o, (nb, dg) in enumerate(outs):
         a, R = f.spec.sweep[o // nr], f.spec.Rs[o % nr]
-        e_nbr, e_deg, _ = oracle.prune_graph(f.w.X, f.o_nbr, f.o_deg, *a, R, nodes=f.nodes)
+        e_nbr, e_deg, _ = oracle.prune_graph(f.w.X, f.o_nbr, f.o_deg, *a, R, nodes=f.nodes,
+                                             threads=THREADS)
         got_nbr, got_deg = _np(nb)[f.nodes], _np(dg)[f.nodes]
         bad = np.nonzero((got_nbr != e_nbr).any(axis=1) | (got_deg != e_deg))[0]
         assert bad.size == 0, (f"alpha={a} R={R}: {bad.size} of {f.nodes.size} sampled rows "
@@ -118,7 +121,8 @@ def test_sift_full_plain_matches_batched(sift_full):
     p_nb, p_dg = f.g.prune_plain(a, R)
     b_nb, b_dg = f.g.prune_sweep([a], [R])[0]
     assert torch.equal(p_dg, b_dg) and torch.equal(p_nb, b_nb)
-    e_nbr, e_deg, _ = oracle.prune_graph(f.w.X, f.o_nbr, f.o_deg, *a, R, nodes=f.nodes)
+    e_nbr, e_deg, _ = oracle.prune_graph(f.w.X, f.o_nbr, f.o_deg, *a, R, nodes=f.nodes,
+                                         threads=THREADS)
     assert np.array_equal(_np(p_nb)[f.nodes], e_nbr)
     assert np.array_equal(_np(p_dg)[f.nodes], e_deg)
 
@@ -158,4 +162,22 @@ def test_deep_full_sweep_sampled(deep_full):
     outs = f.g.prune_sweep(f.spec.sweep, f.spec.Rs)
     c = f.g.counters()
     _say(f"rechecks per vertex-alpha: {c['rechecks'] / max(1, c['nodes']):.4f}")
+    _check_sampled(f, outs)
+
+
+@pytest.fixture(scope="module")
+def gist_full():
+    return Full("gist_f32", 2_000)
+
+
+def test_gist_full_sweep_sampled(gist_full):
+    """1M x 960 float32 (GIST shape), base lists of up to 96 from the 192-NN
+    lists, the benchmark's sweep: alpha in {11/10, 1} x R in {96, 64, 32} (six
+    outputs, one launch; split-FP16 Gram over 30 accumulator chunks, FP64
+    recheck): 2,000 sampled rows of every output equal the oracle's."""
+    f = gist_full
+    f.g.counters(reset=True)
+    outs = f.g.prune_sweep(f.spec.sweep, f.spec.Rs)
+    c = f.g.counters()
+    _say(f"rechecks per vertex-output: {c['rechecks'] / max(1, c['nodes']):.4f}")
     _check_sampled(f, outs)

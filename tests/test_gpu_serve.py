@@ -2,13 +2,16 @@
 varying size, replayed with Poisson arrivals through the request loop, gives
 for every request exactly what the same call gives alone (pruned graphs
 element by element; query ids, distances and visited counts), with
-continuous batching, overlap and budget evictions on, and in FIFO mode."""
+continuous batching, overlap and budget evictions on, and in FIFO mode; and
+every request agrees with the oracle on a sample (300 vertices of each pruned
+graph, the first query of each batch)."""
 import math
 
 import numpy as np
 import pytest
 import torch
 
+import oracle
 import workloads
 
 pytestmark = pytest.mark.gpu
@@ -32,7 +35,44 @@ def setup():
     torch.cuda.synchronize()
     base = Graph(X, nb, dg, w.start)
     Q = torch.from_numpy(w.Q).to(dev)
+    # the base graph equals the oracle's RobustPrune of the same K-NN lists
+    o_nbr, o_deg, _ = oracle.prune_graph(w.X, w.knn, w.knn_deg, 6, 5, 64, threads=8)
+    assert np.array_equal(nb.cpu().numpy(), o_nbr) and np.array_equal(dg.cpu().numpy(), o_deg)
+    _ORACLE["w"] = w
+    _ORACLE["base"] = (o_nbr, o_deg)
     return base, Q
+
+
+_ORACLE = {}
+
+
+def _oracle_sample(meta, seed):
+    """Every prune request on 300 sampled vertices and the first query of
+    every query request against the oracle (RobustPrune of the oracle's own
+    base graph; GreedySearch on the graph the request searched)."""
+    w = _ORACLE["w"]
+    o_nbr, o_deg = _ORACLE["base"]
+    n = w.X.shape[0]
+    nodes = np.sort(np.random.default_rng(seed).choice(n, 300, replace=False)).astype(np.int32)
+    pruned = {}
+
+    def graph_of(a, R):
+        if (a, R) not in pruned:
+            pruned[(a, R)] = oracle.prune_graph(w.X, o_nbr, o_deg, *a, R, threads=8)[:2]
+        return pruned[(a, R)]
+
+    for i, (kind, a, R, data) in enumerate(meta):
+        if kind == "prune":
+            e_nbr, e_deg = graph_of(a, R)
+            assert np.array_equal(data[0].cpu().numpy()[nodes], e_nbr[nodes]), f"request {i}"
+            assert np.array_equal(data[1].cpu().numpy()[nodes], e_deg[nodes]), f"request {i}"
+        else:
+            Qs, k, L, ids, dist, hops = data
+            gn, gd = (o_nbr, o_deg) if a is None else graph_of(a, R)
+            e_ids, e_dist, e_hops = oracle.search(w.X, gn, gd, w.start, Qs[:1].cpu().numpy(), k, L)
+            assert np.array_equal(ids[:1].cpu().numpy(), e_ids), f"request {i}: ids"
+            assert np.array_equal(dist[:1].cpu().numpy(), e_dist), f"request {i}: distances"
+            assert np.array_equal(hops[:1].cpu().numpy(), e_hops), f"request {i}: visited"
 
 
 def _trace(server, base, Q, n_req, seed):
@@ -116,6 +156,7 @@ def test_alone_equals_mix(setup, fifo):
     server.close()
     torch.cuda.synchronize()
     _alone(base, meta)
+    _oracle_sample(meta, seed=fifo)
     n_queries = sum(m[3][0].shape[0] for m in meta if m[0] == "query")
     assert stats["searched_queries"] == n_queries
     if fifo:
