@@ -167,6 +167,33 @@ rp_status rp_search(rp_graph_t g, const void* queries, int64_t nq, int32_t k, in
                     int32_t* out_ids, double* out_dist, int32_t* out_hops, void* stream);
 
 /*
+ * rp_knn_u8 -- exact K nearest neighbours of uint8 points: the input lists of
+ * the base graphs.  The experiments of Section 4 start from a Vamana index
+ * built by RobustPrune (Algorithm 1) over candidate lists; here the candidate
+ * list of a point is its K nearest points, and the base graph is RobustPrune
+ * of that list (rp_load_graph on the lists, then rp_prune).
+ *   points   : n x d uint8, row-major, 16-byte aligned; d a multiple of 16 in
+ *              [16, 256]; 1 <= n < 2^31.
+ *   query_ids: nq point ids whose lists are computed (nullable: points
+ *              0 .. nq - 1).
+ *   cand_ids : nc distinct point ids the lists are drawn from (nullable:
+ *              points 0 .. nc - 1).
+ *   K        : 1 <= K <= 128.
+ *   out_ids  : nq x K int32; row i lists the K candidates nearest to
+ *              query_ids[i] in ascending (S, id) order, S the exact squared
+ *              distance, the query itself excluded; -1 pads a row when fewer
+ *              candidates exist.
+ * A query or candidate id outside [0, n) is ignored (the query's row is all
+ * -1; the candidate is never listed).  All arrays are device arrays.  When
+ * the candidates are split across workgroups (few queries), the partial
+ * lists take a workspace of slices x nq x 1 KiB, allocated and freed in
+ * stream order on `stream` (RP_ENOMEM if that fails).
+ */
+rp_status rp_knn_u8(const uint8_t* points, int64_t n, int32_t d, const int32_t* query_ids,
+                    int64_t nq, const int32_t* cand_ids, int64_t nc, int32_t K,
+                    int32_t* out_ids, void* stream);
+
+/*
  * rp_read_counters -- copy the graph's device counters to *out (host) and,
  * if reset != 0, zero them.  Synchronises `stream`.
  */

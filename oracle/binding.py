@@ -219,8 +219,16 @@ def search(X: np.ndarray, nbr: np.ndarray, deg: np.ndarray, start: int, Q: np.nd
     return ids, dist, hops
 
 
-def groundtruth(X: np.ndarray, Q: np.ndarray, k: int):
-    """Exact k nearest points of each query by (S, id), brute force."""
+def groundtruth(X: np.ndarray, Q: np.ndarray, k: int, threads: int = 1):
+    """Exact k nearest points of each query by (S, id), brute force.
+    threads > 1 runs the single-threaded routine on disjoint query shards."""
+    if threads > 1 and Q.shape[0] > 1:
+        from concurrent.futures import ThreadPoolExecutor
+
+        parts = [p for p in np.array_split(np.arange(Q.shape[0]), threads) if p.size]
+        with ThreadPoolExecutor(max_workers=len(parts)) as ex:
+            res = list(ex.map(lambda idx: groundtruth(X, Q[idx], k), parts))
+        return np.concatenate(res)
     lib = _load()
     X = np.ascontiguousarray(X)
     Q = np.ascontiguousarray(Q, dtype=X.dtype)

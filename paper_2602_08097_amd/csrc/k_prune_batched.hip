@@ -1,8 +1,10 @@
 // k_prune_batched.hip -- dispatch of the batched RP-Tuning sweep.
 //
-// Out-lists of at most 64 ids run the int8-MFMA kernel for uint8 points
-// (k_prune_u8.hip) or the FP16-MFMA kernel with FP64 recheck for float32
-// points (k_prune_f32.hip); other shapes run the plain kernel once per output.
+// uint8 points with out-lists of at most 64 ids run the int8-MFMA kernel
+// (k_prune_u8.hip), of 65..128 ids at d <= 128 its four-block form
+// (k_prune_u8_wide.hip); float32 points with out-lists of at most 96 ids run
+// the FP16-MFMA kernel with FP64 recheck (k_prune_f32.hip); other shapes run
+// the plain kernel once per output.
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -35,6 +37,10 @@ void set_tuned_waves(const TuneKey& k, int waves) {
 bool prune_u8_supported(const GraphView& g);
 hipError_t launch_prune_u8(const GraphView& g, const SweepArgs& a, DevCounters* ctr,
                            hipStream_t s);
+bool prune_u8_wide_supported(const GraphView& g);
+hipError_t launch_prune_u8_wide(const GraphView& g, const SweepArgs& a, DevCounters* ctr,
+                                hipStream_t s);
+int prune_u8_wide_wave_lds(const GraphView& g);
 bool prune_f32_supported(const GraphView& g);
 int prune_u8_wave_lds(const GraphView& g);
 int prune_f32_wave_lds(const GraphView& g);
@@ -43,12 +49,14 @@ hipError_t launch_prune_f32(const GraphView& g, const SweepArgs& a, DevCounters*
 
 int batched_kernel(const GraphView& g) {
   if (prune_u8_supported(g)) return kKernelU8;
+  if (prune_u8_wide_supported(g)) return kKernelU8Wide;
   if (prune_f32_supported(g)) return kKernelF32;
   return 0;
 }
 
 int batched_wave_lds(const GraphView& g) {
   if (prune_u8_supported(g)) return prune_u8_wave_lds(g);
+  if (prune_u8_wide_supported(g)) return prune_u8_wide_wave_lds(g);
   if (prune_f32_supported(g)) return prune_f32_wave_lds(g);
   return 0;
 }
@@ -56,6 +64,7 @@ int batched_wave_lds(const GraphView& g) {
 hipError_t launch_prune_batched(const GraphView& g, const SweepArgs& a, DevCounters* ctr,
                                 hipStream_t s) {
   if (prune_u8_supported(g)) return launch_prune_u8(g, a, ctr, s);
+  if (prune_u8_wide_supported(g)) return launch_prune_u8_wide(g, a, ctr, s);
   if (prune_f32_supported(g)) return launch_prune_f32(g, a, ctr, s);
   for (int o = 0; o < a.n_out; ++o) {
     const SweepOut& out = a.out[o];

@@ -42,63 +42,17 @@
 //              alpha; a smaller R is a prefix.
 //  a8  write:  kept ranks are scattered to their positions (popcount of the
 //              kept ranks before them), -1 padded.
-#include "dev_common.h"
+#include "u8_common.h"
 
 namespace rp {
 
-typedef int v4i __attribute__((ext_vector_type(4)));
-typedef int v16i __attribute__((ext_vector_type(16)));
+using namespace u8;
 
 namespace {
 
 constexpr int kDecisionBytes = 3072;  // decision tile: the blocks on and above the diagonal
 constexpr int kMaxDimU8 = 256;
 constexpr int kWaveLdsU8 = kDecisionBytes + 64 * 4;  // + -16 |u|^2 by rank
-
-// floor(den2 * s / num2) for s < 2^28, exact, from M = floor(2^60 den2 / num2) + 1:
-// 0 < s (M / 2^60 - den2 / num2) < 2^-32 < 1 / num2, less than the gap between a
-// non-integer quotient and the next integer, so floor(16 s M / 2^64) is the
-// floor (two 32 x 32 -> 64-bit multiply-adds).
-__device__ __forceinline__ int32_t alpha_threshold(uint64_t M, uint32_t s) {
-  const uint64_t s16 = (uint64_t)(s << 4);
-  const uint64_t lo = s16 * (uint64_t)(uint32_t)M;
-  const uint64_t hi = s16 * (M >> 32) + (lo >> 32);
-  return (int32_t)(uint32_t)(hi >> 32);
-}
-
-// The decision bounds of this lane's tile column j.  Pair (i, j) is pruned at
-// alpha_k  <=>  S(i, j) <= T_k(j)  <=>  y = 2 G(i, j) - |u_i|^2 >= U_k = |u_j|^2 - T_k(j).
-// On Y = 16 y with B_k = 16 U_k and A_k = B_k - w_k, w_k = 2^(k mod 4), the median
-// med3(Y, A_k, B_k) - A_k is w_k when Y >= B_k and 0 otherwise (Y and B_k are
-// multiples of 16 > w_k), so the code 2^c - 1 is a sum of medians offset by
-// -sum A_k: alphas 0..3 in the low nibble, 4..7 in the high one.
-template <int NA>
-struct ColBounds {
-  int32_t A[NA], B[NA];
-  int32_t off_lo, off_hi;
-};
-
-template <int NA>
-__device__ __forceinline__ ColBounds<NA> col_bounds(int32_t ncol16, const int32_t (&T)[NA]) {
-  ColBounds<NA> cb;
-  cb.off_lo = 0;
-  cb.off_hi = 0;
-#pragma unroll
-  for (int k = 0; k < NA; ++k) {
-    cb.B[k] = ncol16 - 16 * T[k];
-    cb.A[k] = cb.B[k] - (1 << (k & 3));
-    if (k < 4) cb.off_lo -= cb.A[k];
-    else cb.off_hi -= cb.A[k];
-  }
-  return cb;
-}
-
-// One v_med3_i32 (the compiler keeps min(max()) of register bounds as two).
-__device__ __forceinline__ int32_t med3_i32(int32_t x, int32_t lo, int32_t hi) {
-  int32_t r;
-  asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
-  return r;
-}
 
 // a1: the list of p (row and degree loads in flight together).
 __device__ __forceinline__ int load_list(const GraphView& g, int64_t p, int lane) {
@@ -111,31 +65,6 @@ struct Front {
   uint64_t valid_mask;
   int id_rank;
 };
-
-__device__ __forceinline__ v4i shift_u8(v4i x) {
-  x.x ^= 0x80808080;
-  x.y ^= 0x80808080;
-  x.z ^= 0x80808080;
-  x.w ^= 0x80808080;
-  return x;
-}
-
-__device__ __forceinline__ v4i shfl_v4i(v4i x, int src) {
-  v4i y;
-  y.x = __shfl(x.x, src, 64);
-  y.y = __shfl(x.y, src, 64);
-  y.z = __shfl(x.z, src, 64);
-  y.w = __shfl(x.w, src, 64);
-  return y;
-}
-
-__device__ __forceinline__ int sdot16(v4i a, v4i b, int acc) {
-  acc = __builtin_amdgcn_sdot4(a.x, b.x, acc, false);
-  acc = __builtin_amdgcn_sdot4(a.y, b.y, acc, false);
-  acc = __builtin_amdgcn_sdot4(a.z, b.z, acc, false);
-  acc = __builtin_amdgcn_sdot4(a.w, b.w, acc, false);
-  return acc;
-}
 
 // The decision codes of one 32 x 32 block (rows of block BI, columns of block
 // BJ) from its Gram accumulator.  The diagonal blocks also code the columns up
@@ -547,16 +476,15 @@ bool prune_u8_supported(const GraphView& g) {
          g.n <= (1ll << 30) && (((uintptr_t)g.X) & 15) == 0;
 }
 
-hipError_t launch_prune_u8(const GraphView& g, const SweepArgs& a_in, DevCounters* ctr,
-                           hipStream_t s) {
-  (void)ctr;
-  // the kernel takes the alphas in ascending order (num_a den_b vs num_b den_a)
+// The kernels take the alphas in ascending order (num_a^2 den_b^2 against
+// num_b^2 den_a^2), each with its reciprocal-multiply threshold constant; the
+// outputs move with their alphas (outputs are alpha-major: o = alpha * nr + iR).
+SweepArgs u8_sweep_ascending(const SweepArgs& a_in) {
   SweepArgs a = a_in;
   int order[kMaxAlphas];
   for (int i = 0; i < a_in.n_alpha; ++i) order[i] = i;
   for (int i = 1; i < a_in.n_alpha; ++i) {
     int v = order[i], j = i - 1;
-    // compare alpha_v < alpha_order[j] on squares: num2_v den2_o < num2_o den2_v
     while (j >= 0 && (uint64_t)a_in.num2[v] * a_in.den2[order[j]] <
                          (uint64_t)a_in.num2[order[j]] * a_in.den2[v]) {
       order[j + 1] = order[j];
@@ -564,7 +492,6 @@ hipError_t launch_prune_u8(const GraphView& g, const SweepArgs& a_in, DevCounter
     }
     order[j + 1] = v;
   }
-  // outputs are alpha-major (o = alpha * n_R + iR); permute them with the alphas
   const int nr = a_in.n_out / a_in.n_alpha;
   for (int k = 0; k < a_in.n_alpha; ++k) {
     a.num2[k] = a_in.num2[order[k]];
@@ -576,6 +503,13 @@ hipError_t launch_prune_u8(const GraphView& g, const SweepArgs& a_in, DevCounter
       a.out[k * nr + ir].alpha_idx = k;
     }
   }
+  return a;
+}
+
+hipError_t launch_prune_u8(const GraphView& g, const SweepArgs& a_in, DevCounters* ctr,
+                           hipStream_t s) {
+  (void)ctr;
+  const SweepArgs a = u8_sweep_ascending(a_in);
   int idbits = 1;
   while ((1ll << idbits) < g.n) ++idbits;
   Launch L;

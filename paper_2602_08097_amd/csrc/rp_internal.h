@@ -93,6 +93,15 @@ hipError_t launch_prune_batched(const GraphView& g, const SweepArgs& a, DevCount
                                 hipStream_t s);
 hipError_t launch_gram_error_f32(const GraphView& g, const int32_t* nodes, int64_t n_nodes,
                                  GramErrorStats* stats, DevCounters* ctr, hipStream_t s);
+// Exact K-NN of uint8 points (k_knn_u8.hip): supported dimensions, the number
+// of candidate slices for a call, the workspace those slices need (0 for one
+// slice), and the launch.
+bool knn_u8_supported(int d);
+int knn_u8_slices(int64_t nq, int64_t nc);
+size_t knn_u8_workspace_bytes(int64_t nq, int slices);
+hipError_t launch_knn_u8(const uint8_t* X, int64_t n, int32_t d, const int32_t* qids, int64_t nq,
+                         const int32_t* cids, int64_t nc, int32_t K, int32_t* out,
+                         uint64_t* workspace, int slices, hipStream_t s);
 bool prune_f32_shape_ok(const GraphView& g);   // shape the float32 batched kernel serves
 bool prune_f32_supported(const GraphView& g);  // ... and its frame exponents are set
 hipError_t launch_search(const GraphView& g, const void* Q, int64_t nq, int32_t k, int32_t L,
@@ -115,13 +124,14 @@ inline double f32_rel_bound(int d) {
 // prune kernels, per graph shape and sweep shape.  Untuned shapes use 1.
 constexpr int kKernelU8 = 1;
 constexpr int kKernelF32 = 2;
+constexpr int kKernelU8Wide = 3;
 constexpr int kMaxLdsPerGroup = 65536;
 struct TuneKey {
   int32_t kernel, dtype, d, r_max, n_alpha, n_out;
 };
 int tuned_waves(const TuneKey& k);           // 0 if the shape is not tuned
 void set_tuned_waves(const TuneKey& k, int waves);
-int batched_kernel(const GraphView& g);      // kKernelU8, kKernelF32 or 0 (plain)
+int batched_kernel(const GraphView& g);      // kKernelU8, kKernelU8Wide, kKernelF32 or 0 (plain)
 int batched_wave_lds(const GraphView& g);    // LDS bytes per wavefront of that kernel
 // waves per workgroup to launch with: the tuned value, else 1; never more than
 // the LDS per workgroup allows

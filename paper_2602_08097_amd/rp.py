@@ -58,7 +58,7 @@ REQ_PRUNE = 1
 REQ_QUERY = 2
 
 EXPORTS = ["rp_load_graph", "rp_graph_derive", "rp_prune", "rp_prune_sweep", "rp_prune_plain",
-           "rp_prune_sweep_unsorted",
+           "rp_prune_sweep_unsorted", "rp_knn_u8",
            "rp_search", "rp_read_counters", "rp_free_graph", "rp_last_error",
            "rp_plan_sweep", "rp_plan_launch", "rp_plan_free",
            "rp_autotune_sweep", "rp_tune_set", "rp_tune_get", "rp_gram_error",
@@ -90,6 +90,8 @@ def load_library(path: str = LIB_PATH):
                                    C.POINTER(vp), C.POINTER(vp), vp]
     lib.rp_prune_sweep_unsorted.restype = i32
     lib.rp_prune_sweep_unsorted.argtypes = lib.rp_prune_sweep.argtypes
+    lib.rp_knn_u8.restype = i32
+    lib.rp_knn_u8.argtypes = [vp, i64, i32, vp, i64, vp, i64, i32, vp, vp]
     lib.rp_search.restype = i32
     lib.rp_search.argtypes = [vp, vp, i64, i32, i32, vp, vp, vp, vp]
     lib.rp_read_counters.restype = i32
@@ -161,6 +163,33 @@ def as_alpha(a) -> Tuple[int, int]:
     if isinstance(a, tuple):
         return int(a[0]), int(a[1])
     return int(a.numerator), int(a.denominator)
+
+
+def knn_u8(points: torch.Tensor, K: int, query_ids: Optional[torch.Tensor] = None,
+           cand_ids: Optional[torch.Tensor] = None, nq: Optional[int] = None,
+           nc: Optional[int] = None, out: Optional[torch.Tensor] = None, stream=None):
+    """Exact K nearest neighbours (rp_knn_u8): an (nq, K) int32 tensor of
+    candidate ids in ascending (S, id) order, the query itself excluded, -1
+    padded.  query_ids / cand_ids: int32 device tensors of point ids (None:
+    the first nq / nc points, by default all of them)."""
+    lib = load_library()
+    _need_cuda(points, query_ids, cand_ids)
+    if points.dtype != torch.uint8 or points.dim() != 2:
+        raise TypeError("points must be a 2-D uint8 tensor")
+    for t in (query_ids, cand_ids):
+        if t is not None and t.dtype != torch.int32:
+            raise TypeError("ids must be int32")
+    n, d = points.shape
+    nq = int(query_ids.numel()) if query_ids is not None else int(n if nq is None else nq)
+    nc = int(cand_ids.numel()) if cand_ids is not None else int(n if nc is None else nc)
+    if out is None:
+        out = torch.empty((nq, int(K)), dtype=torch.int32, device=points.device)
+    _need_cuda(out)
+    if tuple(out.shape) != (nq, int(K)) or out.dtype != torch.int32:
+        raise ValueError(f"out must be int32 ({nq}, {K})")
+    _check(lib.rp_knn_u8(points.data_ptr(), n, d, _ptr(query_ids), nq, _ptr(cand_ids), nc,
+                         int(K), out.data_ptr(), _stream_ptr(stream)))
+    return out
 
 
 class Graph:

@@ -13,7 +13,7 @@ def _declared():
     names = set()
     for h in HEADERS:
         src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
-        names |= set(re.findall(r"\b(rp_[a-z_]+)\s*\(", src))
+        names |= set(re.findall(r"\b(rp_[a-z0-9_]+)\s*\(", src))
     return sorted(names)
 
 

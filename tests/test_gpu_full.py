@@ -88,6 +88,29 @@ def _check_sampled(f, outs):
         _say(f"alpha={a[0]}/{a[1]} R={R}: {f.nodes.size} sampled rows identical")
 
 
+def test_sift_full_knn_lists(sift_full):
+    """The 128-NN lists of all 1M points from rp_knn_u8 (int8 MFMA, exact
+    (S, id) order): 300 sampled rows equal the oracle's brute force; every row
+    equals the workload's integer-keyed lists."""
+    import time
+
+    from paper_2602_08097_amd import knn_u8
+
+    f = sift_full
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    got = knn_u8(f.X, 128)
+    torch.cuda.synchronize()
+    _say(f"rp_knn_u8 1M x 128, K = 128: {time.perf_counter() - t0:.2f} s")
+    got = _np(got)
+    smp = f.nodes[:300]
+    gt = oracle.groundtruth(f.w.X, f.w.X[smp], 129, threads=THREADS)
+    for r, q in enumerate(smp):
+        want = [int(i) for i in gt[r] if int(i) != int(q)][:128]
+        assert got[q].tolist() == want, int(q)
+    assert np.array_equal(got, f.w.knn)
+
+
 def test_sift_full_sweep_sampled(sift_full):
     """1M x 128 uint8, the benchmark's sweep launch (4 alphas, R = 64): the
     20,000 sampled rows equal the oracle's, element by element."""
