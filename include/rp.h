@@ -194,6 +194,28 @@ rp_status rp_knn_u8(const uint8_t* points, int64_t n, int32_t d, const int32_t* 
                     int32_t* out_ids, void* stream);
 
 /*
+ * rp_knn_u8_noalloc -- rp_knn_u8 for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, hosts that
+ * forbid allocation.  It calls no allocator.  When the candidates are split
+ * into slices, the partial lists go to a fixed workspace of the library:
+ * 64 MiB of device memory per GPU, held until the process ends.
+ *   slices: 1..64 candidate slices (1 needs no workspace; more give few
+ *           queries more parallelism), or 0 for the library's choice reduced
+ *           to fit the workspace.  A call whose slices x nq x 1 KiB exceeds
+ *           64 MiB returns RP_EINVAL before any launch.
+ * Other arguments, outputs and errors as rp_knn_u8; the outputs equal
+ * rp_knn_u8's for every slice count.  Every call on a GPU shares that GPU's
+ * workspace, so calls that overlap in time on one GPU (different streams or
+ * threads without ordering) race; calls ordered on one stream do not.  The
+ * kernels write every partial list before reading it, so nothing left by an
+ * earlier call is read.
+ */
+rp_status rp_knn_u8_noalloc(const uint8_t* points, int64_t n, int32_t d,
+                            const int32_t* query_ids, int64_t nq, const int32_t* cand_ids,
+                            int64_t nc, int32_t K, int32_t slices, int32_t* out_ids,
+                            void* stream);
+
+/*
  * rp_read_counters -- copy the graph's device counters to *out (host) and,
  * if reset != 0, zero them.  Synchronises `stream`.
  */

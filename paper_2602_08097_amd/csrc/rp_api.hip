@@ -148,6 +148,34 @@ rp_status check_outputs(const rp_graph* g, int32_t R, const int32_t* out_nbr,
 
 }  // namespace
 
+namespace rp {
+
+// Argument checks shared by the K-NN entry points.
+rp_status knn_args(const uint8_t* points, int64_t n, int32_t d, const int32_t* query_ids,
+                   int64_t nq, const int32_t* cand_ids, int64_t nc, int32_t K,
+                   const int32_t* out_ids) {
+  if (n < 1 || n >= (1ll << 31)) return fail(RP_EINVAL, "n must be in [1, 2^31)");
+  if (!rp::knn_u8_supported(d))
+    return fail(RP_EINVAL, "d must be a multiple of 16 in [16, 256] (got %d)", d);
+  if (K < 1 || K > 128) return fail(RP_EINVAL, "K must be in [1, 128] (got %d)", K);
+  if (nq < 0 || nq >= (1ll << 31) || nc < 0 || nc >= (1ll << 31))
+    return fail(RP_EINVAL, "nq and nc must be in [0, 2^31)");
+  if (!query_ids && nq > n) return fail(RP_EINVAL, "nq > n without query_ids");
+  if (!cand_ids && nc > n) return fail(RP_EINVAL, "nc > n without cand_ids");
+  if (!device_range(points, (size_t)n * d)) return fail(RP_EINVAL, "points is not a device array of n*d bytes");
+  if (((uintptr_t)points & 15) != 0) return fail(RP_EINVAL, "points must be 16-byte aligned");
+  if (nq == 0) return RP_OK;
+  if (query_ids && !device_range(query_ids, (size_t)nq * 4))
+    return fail(RP_EINVAL, "query_ids is not a device array of nq int32");
+  if (cand_ids && nc > 0 && !device_range(cand_ids, (size_t)nc * 4))
+    return fail(RP_EINVAL, "cand_ids is not a device array of nc int32");
+  if (!device_range(out_ids, (size_t)nq * K * 4))
+    return fail(RP_EINVAL, "out_ids is not a device array of nq*K int32");
+  return RP_OK;
+}
+
+}  // namespace rp
+
 extern "C" {
 
 const char* rp_last_error(void) { return rp::last_error(); }
@@ -520,38 +548,11 @@ rp_status rp_search(rp_graph_t g, const void* queries, int64_t nq, int32_t k, in
   return st == RP_OK ? ok() : st;
 }
 
-namespace {
-
-// Argument checks shared by the K-NN entry points.
-rp_status knn_args(const uint8_t* points, int64_t n, int32_t d, const int32_t* query_ids,
-                   int64_t nq, const int32_t* cand_ids, int64_t nc, int32_t K,
-                   const int32_t* out_ids) {
-  if (n < 1 || n >= (1ll << 31)) return fail(RP_EINVAL, "n must be in [1, 2^31)");
-  if (!rp::knn_u8_supported(d))
-    return fail(RP_EINVAL, "d must be a multiple of 16 in [16, 256] (got %d)", d);
-  if (K < 1 || K > 128) return fail(RP_EINVAL, "K must be in [1, 128] (got %d)", K);
-  if (nq < 0 || nq >= (1ll << 31) || nc < 0 || nc >= (1ll << 31))
-    return fail(RP_EINVAL, "nq and nc must be in [0, 2^31)");
-  if (!query_ids && nq > n) return fail(RP_EINVAL, "nq > n without query_ids");
-  if (!cand_ids && nc > n) return fail(RP_EINVAL, "nc > n without cand_ids");
-  if (!device_range(points, (size_t)n * d)) return fail(RP_EINVAL, "points is not a device array of n*d bytes");
-  if (((uintptr_t)points & 15) != 0) return fail(RP_EINVAL, "points must be 16-byte aligned");
-  if (nq == 0) return RP_OK;
-  if (query_ids && !device_range(query_ids, (size_t)nq * 4))
-    return fail(RP_EINVAL, "query_ids is not a device array of nq int32");
-  if (cand_ids && nc > 0 && !device_range(cand_ids, (size_t)nc * 4))
-    return fail(RP_EINVAL, "cand_ids is not a device array of nc int32");
-  if (!device_range(out_ids, (size_t)nq * K * 4))
-    return fail(RP_EINVAL, "out_ids is not a device array of nq*K int32");
-  return RP_OK;
-}
-
-}  // namespace
 
 rp_status rp_knn_u8(const uint8_t* points, int64_t n, int32_t d, const int32_t* query_ids,
                     int64_t nq, const int32_t* cand_ids, int64_t nc, int32_t K,
                     int32_t* out_ids, void* stream) {
-  rp_status st = knn_args(points, n, d, query_ids, nq, cand_ids, nc, K, out_ids);
+  rp_status st = rp::knn_args(points, n, d, query_ids, nq, cand_ids, nc, K, out_ids);
   if (st != RP_OK || nq == 0) return st == RP_OK ? ok() : st;
   hipStream_t s = (hipStream_t)stream;
   const int slices = rp::knn_u8_slices(nq, nc);

@@ -96,6 +96,9 @@ hipError_t launch_gram_error_f32(const GraphView& g, const int32_t* nodes, int64
 // Exact K-NN of uint8 points (k_knn_u8.hip): supported dimensions, the number
 // of candidate slices for a call, the workspace those slices need (0 for one
 // slice), and the launch.
+rp_status knn_args(const uint8_t* points, int64_t n, int32_t d, const int32_t* query_ids,
+                   int64_t nq, const int32_t* cand_ids, int64_t nc, int32_t K,
+                   const int32_t* out_ids);
 bool knn_u8_supported(int d);
 int knn_u8_slices(int64_t nq, int64_t nc);
 size_t knn_u8_workspace_bytes(int64_t nq, int slices);

@@ -58,7 +58,7 @@ REQ_PRUNE = 1
 REQ_QUERY = 2
 
 EXPORTS = ["rp_load_graph", "rp_graph_derive", "rp_prune", "rp_prune_sweep", "rp_prune_plain",
-           "rp_prune_sweep_unsorted", "rp_knn_u8",
+           "rp_prune_sweep_unsorted", "rp_knn_u8", "rp_knn_u8_noalloc",
            "rp_search", "rp_read_counters", "rp_free_graph", "rp_last_error",
            "rp_plan_sweep", "rp_plan_launch", "rp_plan_free",
            "rp_autotune_sweep", "rp_tune_set", "rp_tune_get", "rp_gram_error",
@@ -92,6 +92,8 @@ def load_library(path: str = LIB_PATH):
     lib.rp_prune_sweep_unsorted.argtypes = lib.rp_prune_sweep.argtypes
     lib.rp_knn_u8.restype = i32
     lib.rp_knn_u8.argtypes = [vp, i64, i32, vp, i64, vp, i64, i32, vp, vp]
+    lib.rp_knn_u8_noalloc.restype = i32
+    lib.rp_knn_u8_noalloc.argtypes = [vp, i64, i32, vp, i64, vp, i64, i32, i32, vp, vp]
     lib.rp_search.restype = i32
     lib.rp_search.argtypes = [vp, vp, i64, i32, i32, vp, vp, vp, vp]
     lib.rp_read_counters.restype = i32
@@ -189,6 +191,26 @@ def knn_u8(points: torch.Tensor, K: int, query_ids: Optional[torch.Tensor] = Non
         raise ValueError(f"out must be int32 ({nq}, {K})")
     _check(lib.rp_knn_u8(points.data_ptr(), n, d, _ptr(query_ids), nq, _ptr(cand_ids), nc,
                          int(K), out.data_ptr(), _stream_ptr(stream)))
+    return out
+
+
+def knn_u8_noalloc(points: torch.Tensor, K: int, out: torch.Tensor,
+                   query_ids: Optional[torch.Tensor] = None,
+                   cand_ids: Optional[torch.Tensor] = None, nq: Optional[int] = None,
+                   nc: Optional[int] = None, slices: int = 0, stream=None) -> torch.Tensor:
+    """rp_knn_u8_noalloc: knn_u8 into the caller's `out` with the library's
+    fixed workspace (no device allocation); `slices` as in include/rp.h."""
+    lib = load_library()
+    _need_cuda(points, query_ids, cand_ids, out)
+    if points.dtype != torch.uint8 or points.dim() != 2:
+        raise TypeError("points must be a 2-D uint8 tensor")
+    n, d = points.shape
+    nq = int(query_ids.numel()) if query_ids is not None else int(n if nq is None else nq)
+    nc = int(cand_ids.numel()) if cand_ids is not None else int(n if nc is None else nc)
+    if tuple(out.shape) != (nq, int(K)) or out.dtype != torch.int32:
+        raise ValueError(f"out must be int32 ({nq}, {K})")
+    _check(lib.rp_knn_u8_noalloc(points.data_ptr(), n, d, _ptr(query_ids), nq, _ptr(cand_ids),
+                                 nc, int(K), int(slices), out.data_ptr(), _stream_ptr(stream)))
     return out
 
 
