@@ -1,16 +1,25 @@
 #!/usr/bin/env python3
-"""Benchmark: RP-Tuning prune sweep (and GreedySearch) on one MI355X.
+"""Benchmark: RP-Tuning prune sweeps (and GreedySearch) on one MI355X.
 
 One step = one pass of the prune hot path over the whole graph: RobustPrune
-of every vertex's base out-list at every alpha of the sweep (one launch of
-the batched kernel).  Default workload: 1,000,000 uint8 points, d = 128,
-64-component Gaussian mixture; base graph = exact 128-NN lists pruned at
-alpha = 6/5, R = 64; sweep alpha in {23/20, 11/10, 21/20, 1}, R = 64.
+of every vertex's base out-list at every (alpha, R) of the sweep (one launch
+of the batched kernel).  The headline workload (`value`): 1,000,000 uint8
+points, d = 128, 64-component Gaussian mixture; base graph = exact 128-NN
+lists (int8 MFMA brute force) pruned at alpha = 6/5, R = 64; sweep alpha in
+{23/20, 11/10, 21/20, 1}, R = 64.  The same line carries one record per
+further workload (`configs`): the 10,000 x 32 float32 workload, the
+Deep-shaped 1M x 96 float32 sweep of 8 alphas over uneven degrees and the
+GIST-shaped 1M x 960 float32 sweep of 2 alphas x 3 bounds.
 
-Inputs are resident in HBM before the timed region.  The plain one-workgroup
-per-vertex kernel is timed on the same inputs (one launch per alpha), the
-search leg reports QPS and recall on the pruned graphs, and the CPU oracle is
-timed on a bounded node sample on the host.
+Per workload: inputs resident in HBM before the timed region; base-graph
+build time; sweep time from HIP events on the launch stream; nodes/s,
+node-prunes/s, input and output edges/s; the HBM roofline of the sweep
+kernel (algorithmic bytes) with its counter-measured traffic when the
+committed profile matches the kernel source; matrix-unit use; rechecks and
+the measured distance error (float32); the plain kernel on the same inputs;
+search QPS and recall per (graph, L), latency p50/p99 per batch size and the
+recall-QPS frontier; the CPU oracle on a bounded vertex sample, pinned to one
+core.  The headline workload also runs a short serving mix.
 
 Prints ONE JSON line.
 """
@@ -33,27 +42,38 @@ HBM_PEAK_GBS = 8000.0
 
 COPY_BYTES = 256 << 20
 PROFILES = os.path.join(ROOT, "profiles")
-KERNEL_SRC = {"u8": os.path.join(ROOT, "paper_2602_08097_amd", "csrc", "k_prune_u8.hip")}
+_CSRC = os.path.join(ROOT, "paper_2602_08097_amd", "csrc")
+# the sources each sweep kernel is compiled from (a counter profile is used
+# only while they are unchanged)
+KERNEL_SRC = {
+    "prune_u8_kernel": ["k_prune_u8.hip", "u8_common.h", "dev_common.h", "rp_internal.h"],
+    "prune_u8_wide_kernel": ["k_prune_u8_wide.hip", "u8_common.h", "dev_common.h",
+                             "rp_internal.h"],
+    "prune_f32_kernel": ["k_prune_f32.hip", "dev_common.h", "rp_internal.h"],
+    "prune_plain_kernel": ["k_prune_plain.hip", "dev_common.h", "rp_internal.h"],
+}
+DEFAULT_CONFIGS = "sift_u8,tiny,deep_f32,gist_f32"
 
 
-def source_digest(path):
+def source_digest(kernel):
     import hashlib
 
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in KERNEL_SRC[kernel]:
+        with open(os.path.join(_CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
-def measured_traffic(dtype, n):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, if it was taken on the current kernel source and workload size."""
-    import numpy as np
-
-    path = os.path.join(PROFILES, "prune_u8_sift_u8_traffic.json")
-    if dtype != np.uint8 or not os.path.exists(path):
+def measured_traffic(kernel, workload, n):
+    """HBM bytes per launch of the sweep kernel from the committed counter
+    summary, if it was taken on the current kernel sources and this size."""
+    path = os.path.join(PROFILES, f"{kernel}_{workload}_traffic.json")
+    if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("source_sha256_16") != source_digest(KERNEL_SRC["u8"]) or t.get("n") != n:
+    if t.get("source_sha256_16") != source_digest(kernel) or t.get("n") != n:
         return None
     return t.get("traffic_bytes_per_launch")
 
@@ -77,8 +97,13 @@ def _col(row, *names):
     raise KeyError(f"none of {names} in {list(row)}")
 
 
-def summarize_profile(root):
-    """Summarise the three rocprofv3 runs under root (trace/, fetch/, write/)."""
+def summarize_profile(root, kernel=None, workload=None, n=None):
+    """Summarise the rocprofv3 runs under root (trace/ and one directory per
+    counter pass).  With kernel/workload/n, also write the calibrated traffic
+    of that kernel (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from the
+    reference kernels of known size in the same runs) with the digest of its
+    current sources to <root>/summary/<kernel>_<workload>_traffic.json (the
+    file the benchmark reads from profiles/)."""
     out = os.path.join(root, "summary")
     os.makedirs(out, exist_ok=True)
     stats = _read_csvs(os.path.join(root, "trace"), "kernel_stats.csv")
@@ -113,21 +138,37 @@ def summarize_profile(root):
     with open(os.path.join(out, "counters.json"), "w") as f:
         json.dump(res, f, indent=1)
     print(json.dumps(res, indent=1))
+    if kernel:
+        fetch = [v for k, v in res.items() if k.startswith("FETCH_SIZE") and kernel + "<" in k
+                 or k.startswith("FETCH_SIZE") and k.endswith(kernel)]
+        write = [v for k, v in res.items() if k.startswith("WRITE_SIZE") and kernel + "<" in k
+                 or k.startswith("WRITE_SIZE") and k.endswith(kernel)]
+        if fetch and write:
+            t = {"kernel": kernel, "workload": workload, "n": n,
+                 "source_sha256_16": source_digest(kernel),
+                 "fetch_kib_per_dispatch": max(fetch), "write_kib_per_dispatch": max(write),
+                 "fetch_calibration": 2.0, "write_calibration": 1.0,
+                 "traffic_bytes_per_launch": int(1024 * (2.0 * max(fetch) + max(write)))}
+            path = os.path.join(out, f"{kernel}_{workload}_traffic.json")
+            with open(path, "w") as f:
+                json.dump(t, f, indent=1)
+            print(f"wrote {path}: {t['traffic_bytes_per_launch']} bytes per launch")
 
 
-def load_or_build(args, spec, dev):
+def load_or_build(args, name, spec, dev):
     import numpy as np
 
     import workloads
 
-    if args.cache and os.path.exists(args.cache):
-        z = np.load(args.cache, allow_pickle=False)
+    cache = args.cache.replace("{config}", name) if args.cache else None
+    if cache and os.path.exists(cache):
+        z = np.load(cache, allow_pickle=False)
         tg = z["targets"] if z["targets"].size else None
         return workloads.Workload(spec, z["X"], z["Q"], z["knn"], z["knn_deg"], int(z["start"]),
                                   tg, z["sample"])
-    w = workloads.build(args.config, n=args.n, nq=args.nq, device=dev)
-    if args.cache:
-        np.savez(args.cache, X=w.X, Q=w.Q, knn=w.knn, knn_deg=w.knn_deg, start=np.int64(w.start),
+    w = workloads.build(name, n=args.n, nq=args.nq, device=dev)
+    if cache:
+        np.savez(cache, X=w.X, Q=w.Q, knn=w.knn, knn_deg=w.knn_deg, start=np.int64(w.start),
                  targets=w.targets if w.targets is not None else np.zeros(0, np.int32),
                  sample=w.sample)
     return w
@@ -184,9 +225,14 @@ def batched_kernel_name(dtype, r_max, d):
     import numpy as np
 
     if dtype == np.uint8:
-        return "prune_u8_kernel" if r_max <= 64 and d % 16 == 0 and d <= 256 else \
-            "prune_plain_kernel"
-    return "prune_f32_kernel" if r_max <= 96 else "prune_plain_kernel"
+        if d % 16 == 0 and r_max <= 64 and d <= 256:
+            return "prune_u8_kernel"
+        if d % 16 == 0 and r_max <= 128 and d <= 128:
+            return "prune_u8_wide_kernel"
+        return "prune_plain_kernel"
+    if r_max <= 64 or (r_max <= 96 and d <= 3408):
+        return "prune_f32_kernel"
+    return "prune_plain_kernel"
 
 
 def exact_gt_u8(X, Q, k, chunk=1024):
@@ -208,16 +254,29 @@ def exact_gt_u8(X, Q, k, chunk=1024):
     return torch.cat(out)
 
 
-def exact_gt_f32(X, Q, k, chunk=256):
-    """Top-k by FP32 squared distance (used for recall only)."""
+def exact_gt_f32(X, Q, k, chunk=128, extra=16):
+    """Top-k by (S, id) with S in FP64 (recall's ground truth): the k + extra
+    smallest of |q|^2 + |x|^2 - 2 <q, x> evaluated in FP64, re-ranked by the
+    directly differenced FP64 S and then by id.  It can differ from the
+    canonical fused-multiply-add order only on pairs within a few FP64 ulps
+    of each other at the k-th place."""
     import torch
 
-    nx = (X * X).sum(1)
+    X64 = X.double()
+    nx = (X64 * X64).sum(1)
     out = []
     for a in range(0, Q.shape[0], chunk):
-        q = Q[a:a + chunk]
-        dist = nx[None, :] - 2.0 * (q @ X.T) + (q * q).sum(1)[:, None]
-        out.append(torch.topk(dist, k, dim=1, largest=False, sorted=True).indices.to(torch.int32))
+        q = Q[a:a + chunk].double()
+        dist = nx[None, :] - 2.0 * (q @ X64.T) + (q * q).sum(1)[:, None]
+        cand = torch.topk(dist, k + extra, dim=1, largest=False, sorted=False).indices
+        diff = X64[cand] - q[:, None, :]
+        s = (diff * diff).sum(-1)
+        # (S, id): sort by id, then stably by S
+        order = torch.argsort(cand, dim=1)
+        cand = torch.gather(cand, 1, order)
+        s = torch.gather(s, 1, order)
+        o2 = torch.sort(s, dim=1, stable=True).indices
+        out.append(torch.gather(cand, 1, o2)[:, :k].to(torch.int32))
     return torch.cat(out)
 
 
@@ -248,36 +307,65 @@ def recall(ids, gt, k):
     return hit / (k * a.shape[0])
 
 
-def cpu_baseline(w, spec, budget_s):
-    """The oracle (single thread) on a node sample of the same sweep."""
+def host_facts():
+    """CPU model and the cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0))}
+
+
+def cpu_baseline(w, spec, budget_s, sample=20_000):
+    """The oracle (single thread, pinned to one core of this process's set)
+    on a vertex sample of the same sweep: the oracle builds its own base rows
+    for the sample from the K-NN lists, then re-prunes them at every
+    (alpha, R) until the budget is spent."""
     import numpy as np
 
     import oracle
     import workloads
 
-    nodes = workloads.node_sample(w.X.shape[0], 40_000)
-    # the oracle builds its own base rows for the sample from the K-NN lists
+    nodes = workloads.node_sample(w.X.shape[0], sample)
     b_nbr, b_deg, _ = oracle.prune_graph(w.X, w.knn, w.knn_deg, *spec.base_alpha, spec.base_R,
-                                         nodes=nodes)
+                                         nodes=nodes, threads=8)
     n = w.X.shape[0]
     full_nbr = np.zeros((n, spec.base_R), np.int32)
     full_deg = np.zeros(n, np.int32)
     full_nbr[nodes] = b_nbr
-    full_deg[nodes] = b_deg
-    done = 0
-    t0 = time.perf_counter()
-    chunk = 500
-    while done < len(nodes) and time.perf_counter() - t0 < budget_s:
-        part = nodes[done:done + chunk]
-        for a in spec.sweep:
-            for R in spec.Rs:
-                oracle.prune_graph(w.X, full_nbr, full_deg, *a, R, nodes=part)
-        done += len(part)
-    dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "nodes/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} sampled vertices x {len(spec.sweep)} alphas x {len(spec.Rs)} R "
-                      f"(base rows from the oracle's own RobustPrune of the K-NN lists), "
-                      f"{dt:.1f} s single-threaded"}
+    full_deg[nodes] = b_deg if w.targets is None else np.minimum(b_deg, w.targets[nodes])
+    allowed = sorted(os.sched_getaffinity(0))
+    core = allowed[0]
+    os.sched_setaffinity(0, {core})  # this thread: the taskset pin of the timed loop
+    done, pairs = 0, 0
+    try:
+        t0 = time.perf_counter()
+        chunk = 250
+        while done < len(nodes) and time.perf_counter() - t0 < budget_s:
+            part = nodes[done:done + chunk]
+            for a in spec.sweep:
+                for R in spec.Rs:
+                    pairs += oracle.prune_graph(w.X, full_nbr, full_deg, *a, R, nodes=part)[2]
+            done += len(part)
+        dt = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, set(allowed))
+    outs = len(spec.sweep) * len(spec.Rs)
+    rec = {"value": done / dt, "unit": "nodes/s", "cores": 1, "kind": "oracle",
+           "sample": f"{done} sampled vertices x {len(spec.sweep)} alphas x {len(spec.Rs)} R "
+                     f"(base rows from the oracle's own RobustPrune of the K-NN lists), "
+                     f"{dt:.1f} s on one core",
+           "node_prunes_per_s": done * outs / dt,
+           "pairs_per_node_prune": pairs / max(1, done * outs),
+           "pinned_core": core}
+    rec.update(host_facts())
+    return rec
 
 
 def serve_trace(spec, n_req, rate, n_graph_ids, Qpool, dev, seed):
@@ -425,79 +513,88 @@ def serve_main(args):
     print(json.dumps(line), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="sift_u8")
-    ap.add_argument("--n", type=int, default=None)
-    ap.add_argument("--nq", type=int, default=None)
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-search", action="store_true")
-    ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--profile", action="store_true",
-                    help="profiling run: a 256 MiB device copy for counter calibration, then "
-                         "the timed sweep only (no plain/search/CPU legs)")
-    ap.add_argument("--cache", metavar="NPZ",
-                    help="load the generated workload from NPZ if present, else generate and save "
-                         "it there (for repeated profiler runs)")
-    ap.add_argument("--serve", action="store_true",
-                    help="serving benchmark: Poisson mix of prune requests and query batches "
-                         "through the request loop vs the one-at-a-time FIFO baseline")
-    ap.add_argument("--rates", default="100,200,400",
-                    help="serving: request arrival rates (requests/s)")
-    ap.add_argument("--requests", type=int, default=2000, help="serving: requests per rate")
-    ap.add_argument("--summarize-profile", metavar="DIR",
-                    help="summarise rocprofv3 output under DIR (trace, fetch, write runs) into "
-                         "DIR/summary and exit")
-    args = ap.parse_args()
+def latency_profile(gg, Q, k, L, stream, batches=(1, 64, 4096), reps=None):
+    """Per-launch latency of GreedySearch at several batch sizes (HIP events
+    on the launch stream): p50, p99 and the QPS of back-to-back batches."""
+    import numpy as np
+    import torch
 
-    if args.summarize_profile:
-        summarize_profile(args.summarize_profile)
-        return
-    if args.serve:
-        if args.gpus != 1:
-            print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
-            sys.exit(2)
-        serve_main(args)
-        return
-    if args.profile:
-        args.no_plain = args.no_search = args.no_cpu = True
+    reps = reps or {1: 200, 64: 100, 4096: 20}
+    out = []
+    nq = Q.shape[0]
+    for B in batches:
+        if B > nq:
+            continue
+        r = reps.get(B, 20)
+        gg.search(Q[:B], k, L, want_dist=False)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(r)]
+        for i, (e0, e1) in enumerate(evs):
+            a = (i * B) % max(1, nq - B + 1)
+            e0.record(stream)
+            gg.search(Q[a:a + B], k, L, want_dist=False)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        ms = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+        out.append({"batch": B, "L": L, "k": k, "launches": r, "p50_ms": float(np.percentile(ms, 50)),
+                    "p99_ms": float(np.percentile(ms, 99)), "qps": B / (ms.mean() * 1e-3)})
+    return out
 
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
-        sys.exit(2)
 
+def frontier(points):
+    """The recall-QPS Pareto frontier (Figures 3-5 plot these curves): the
+    (graph, L) points that no other point beats on both recall and QPS,
+    ascending by recall."""
+    pts = sorted(points, key=lambda r: (-r["recall_at_k"], -r["qps"]))
+    best_qps, keep = -1.0, []
+    for r in pts:
+        if r["qps"] > best_qps:
+            keep.append({"graph": r["graph"], "L": r["L"], "recall_at_k": r["recall_at_k"],
+                         "qps": r["qps"]})
+            best_qps = r["qps"]
+    return sorted(keep, key=lambda r: r["recall_at_k"])
+
+
+def run_config(name, args, dev, headline):
+    """Everything measured on one workload; returns its record."""
     import numpy as np
     import torch
 
     import workloads
-    from paper_2602_08097_amd import Graph
+    from paper_2602_08097_amd import Graph, knn_u8
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    if args.profile:
-        # counter calibration: a plain device copy of a known size
-        # (a fill kernel writes COPY_BYTES; a reduction reads COPY_BYTES)
-        src = torch.randint(0, 255, (COPY_BYTES,), dtype=torch.uint8, device=dev)
-        for _ in range(3):
-            total = src.sum(dtype=torch.int64)
-        torch.cuda.synchronize()
-        del src, total
-    spec = workloads.CONFIGS[args.config]
+    spec = workloads.CONFIGS[name]
     t0 = time.time()
-    w = load_or_build(args, spec, dev)
+    w = load_or_build(args, name, spec, dev)
     n, d = w.X.shape
-    log(f"workload {spec.name}: n={n} d={d} ({time.time() - t0:.1f} s incl. exact {spec.knn_k}-NN)")
-
+    gen_s = time.time() - t0
+    log(f"workload {name}: n={n} d={d} ({gen_s:.1f} s incl. the input K-NN lists)")
     X = torch.from_numpy(w.X).to(dev)
-    knn = torch.from_numpy(w.knn).to(dev)
+    stream = torch.cuda.current_stream()
+    build = {}
+
+    # ---- base graph on the GPU: K-NN lists (uint8: rp_knn_u8), then RobustPrune
     kdeg = torch.from_numpy(w.knn_deg).to(dev)
+    torch.cuda.synchronize()
+    if w.X.dtype == np.uint8 and spec.knn_k <= 128 and d % 16 == 0:
+        tk = time.perf_counter()
+        knn = knn_u8(X, spec.knn_k)
+        torch.cuda.synchronize()
+        build["knn_s"] = time.perf_counter() - tk
+        build["knn"] = f"rp_knn_u8 ({spec.knn_k} nearest of all {n} points, int8 MFMA)"
+        # the generator's integer-keyed lists are the same exact (S, id) order
+        build["knn_equals_generator_lists"] = bool(
+            np.array_equal(knn.cpu().numpy(), w.knn))
+    else:
+        knn = torch.from_numpy(w.knn).to(dev)
+        build["knn"] = "generator lists (FP32 GEMM + top-k on the GPU)"
     g_knn = Graph(X, knn, kdeg, w.start)
+    tb = time.perf_counter()
     base_nbr, base_deg = g_knn.prune(spec.base_alpha, spec.base_R)
+    torch.cuda.synchronize()
+    build["base_prune_s"] = time.perf_counter() - tb
+    build["base_prune_kernel"] = batched_kernel_name(w.X.dtype, spec.knn_k, d)
     if w.targets is not None:
         # uneven out-degrees: keep the first min(t_p, deg) ids of each base list
         base_deg = torch.minimum(base_deg, torch.from_numpy(w.targets).to(dev))
@@ -507,22 +604,24 @@ def main():
     torch.cuda.synchronize()
     g = g_knn.derive(base_nbr, base_deg)
     deg_np = base_deg.cpu().numpy()
-    log(f"base graph alpha={spec.base_alpha} R={spec.base_R}: mean degree {deg_np.mean():.2f}")
+    log(f"base graph alpha={spec.base_alpha} R={spec.base_R}: mean degree {deg_np.mean():.2f} "
+        f"({build})")
 
     nr = len(spec.Rs)
-    outs = [g._outs(spec.Rs[o % nr]) for o in range(len(spec.sweep) * nr)]
-    stream = torch.cuda.current_stream()
+    n_out = len(spec.sweep) * nr
+    outs = [g._outs(spec.Rs[o % nr]) for o in range(n_out)]
 
-    # ---- launch tuning (vertices per workgroup), then the timed sweep -------
+    # ---- launch tuning, then the timed sweep ----------------------------------
     tune = g.autotune_sweep(spec.sweep, spec.Rs, outs=outs)
     log(f"autotune: {tune['waves']} vertices per workgroup (ms for 1/2/4/8: "
         f"{[round(x, 3) for x in tune['ms']]})")
+    steps = args.steps if headline else max(3, min(args.steps, 10))
     for _ in range(args.warmup):
         g.prune_sweep(spec.sweep, spec.Rs, outs=outs)
     torch.cuda.synchronize()
     g.counters(reset=True)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
+           for _ in range(steps)]
     t_start = time.perf_counter()
     for e0, e1 in evs:
         e0.record(stream)
@@ -532,77 +631,86 @@ def main():
     wall = time.perf_counter() - t_start
     kern_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
     ctr = g.counters()
-    ms_per_step = wall * 1e3 / args.steps
-    value = n / (wall / args.steps)
+    ms_per_step = wall * 1e3 / steps
+    value = n / (wall / steps)
     avg_kernel_ms = float(np.mean(kern_ms))
-    out_degs = [o[1].cpu().numpy() for o in outs]
-    log(f"batched sweep: {ms_per_step:.3f} ms/step, kernel {avg_kernel_ms:.3f} ms avg, "
-        f"{value:.3e} nodes/s; mean out-degree per alpha "
-        f"{[round(float(x.mean()), 2) for x in out_degs]}")
+    out_deg_sum = sum(int(o[1].sum().item()) for o in outs)
+    in_edges = int(deg_np.astype(np.int64).sum())
+    log(f"{name} sweep: {ms_per_step:.3f} ms/step, kernel {avg_kernel_ms:.3f} ms avg, "
+        f"{value:.3e} nodes/s")
 
     gram_err = None
-    if w.X.dtype == np.float32 and spec.base_R <= 96:
+    if w.X.dtype == np.float32 and batched_kernel_name(w.X.dtype, spec.base_R, d) == \
+            "prune_f32_kernel":
         smp = torch.from_numpy(w.sample[:2000].astype(np.int32)).to(dev)
         gram_err = g.gram_error(smp)
-        log(f"distance error of the FP16 Gram vs canonical FP64 on 2000 vertices: "
-            f"max rel {gram_err['max_rel']:.3e}, mean rel {gram_err['mean_rel']:.3e}, "
-            f"max error / proven band {gram_err['max_err_over_bound']:.3f} "
-            f"({gram_err['pairs']} pairs)")
+        log(f"distance error vs canonical FP64 on 2000 vertices: max rel "
+            f"{gram_err['max_rel']:.3e}, max error / proven band "
+            f"{gram_err['max_err_over_bound']:.3f}")
 
     esz = 1 if w.X.dtype == np.uint8 else 4
-    Rs_out = [spec.Rs[o % nr] for o in range(len(spec.sweep) * nr)]
+    Rs_out = [spec.Rs[o % nr] for o in range(n_out)]
     abytes = algorithmic_bytes(deg_np, d, esz, Rs_out)
     achieved = abytes / (avg_kernel_ms * 1e-3) / 1e9
+    kname = batched_kernel_name(w.X.dtype, spec.base_R, d)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(w.X.dtype, n),
-                "kernel": batched_kernel_name(w.X.dtype, spec.base_R, d),
+                "traffic": measured_traffic(kname, name, n), "kernel": kname,
                 "algorithmic_bytes_per_launch": abytes,
                 "kernel_ms_avg": round(avg_kernel_ms, 4)}
     mfma = mfma_usage(w.X.dtype, deg_np, d, spec.base_R, avg_kernel_ms)
-    log(f"matrix units: {mfma['executed']} {mfma['unit']} executed "
-        f"({100 * mfma['frac']:.1f}% of peak), Gram useful {mfma['gram_useful']} {mfma['unit']}")
+    rec = {"workload": name, "n": n, "d": d, "dtype": "u8" if esz == 1 else "f32",
+           "sweep": {"alphas": [f"{a}/{b}" for a, b in spec.sweep], "Rs": list(spec.Rs)},
+           "steps": steps, "ms_per_step": ms_per_step, "nodes_per_s": value,
+           "node_prunes_per_s": value * n_out,
+           "input_edges_per_s": in_edges / (wall / steps),
+           "output_edges_per_s": out_deg_sum / (wall / steps),
+           "mean_base_degree": float(deg_np.mean()),
+           "mean_out_degree": out_deg_sum / (n * n_out),
+           "rechecks_per_node_prune": ctr["rechecks"] / max(1, ctr["nodes"]),
+           "vertices_per_workgroup": tune["waves"], "roofline": roofline, "mfma": mfma,
+           "distance_error": gram_err if gram_err is not None else
+           ({"max_rel": 0.0, "mean_rel": 0.0, "note": "uint8: exact int32 distances"}
+            if esz == 1 else None),
+           "build": build, "data_s": gen_s}
 
-    # ---- plain kernel on the same inputs ----------------------------------
-    plain = None
+    # ---- plain kernel on the same inputs ---------------------------------------
     if not args.no_plain:
-        psteps = max(1, min(3, args.steps))
+        # GIST-sized sweeps: one output timed (the plain kernel runs each
+        # output as its own launch), scaled to the sweep
+        one = kname == "prune_f32_kernel" and d > 256
         pouts = [g._outs(R) for R in spec.Rs]
-        for a in spec.sweep:  # warm
-            for ir, R in enumerate(spec.Rs):
-                g.prune_plain(a, R, out=pouts[ir])
+        work = [(spec.sweep[-1], 0)] if one else \
+            [(a, ir) for a in spec.sweep for ir in range(nr)]
+        for a, ir in work[:1]:
+            g.prune_plain(a, spec.Rs[ir], out=pouts[ir])
         torch.cuda.synchronize()
         tp = time.perf_counter()
-        for _ in range(psteps):
-            for a in spec.sweep:
-                for ir, R in enumerate(spec.Rs):
-                    g.prune_plain(a, R, out=pouts[ir])
+        for a, ir in work:
+            g.prune_plain(a, spec.Rs[ir], out=pouts[ir])
         torch.cuda.synchronize()
-        pwall = (time.perf_counter() - tp) / psteps
-        # the plain path agrees with the batched one (last alpha compared)
-        same = bool(torch.equal(pouts[-1][0], outs[-1][0]))
-        plain = {"nodes_per_s": n / pwall, "ms_per_step": pwall * 1e3,
-                 "speedup_batched_vs_plain": (n / (wall / args.steps)) / (n / pwall),
-                 "outputs_identical": same}
-        log(f"plain: {pwall * 1e3:.3f} ms/step, {n / pwall:.3e} nodes/s, identical={same}")
+        pwall = (time.perf_counter() - tp) * (n_out / len(work))
+        a_last, ir_last = work[-1]
+        same = bool(torch.equal(pouts[ir_last][0],
+                                outs[spec.sweep.index(a_last) * nr + ir_last][0]))
+        rec["plain"] = {"nodes_per_s": n / pwall, "ms_per_step": pwall * 1e3,
+                        "timed": "one output, scaled to the sweep" if one else "every output",
+                        "speedup_batched_vs_plain": (ms_per_step and pwall * 1e3 / ms_per_step),
+                        "outputs_identical": same}
+        log(f"plain: {pwall * 1e3:.1f} ms/step ({rec['plain']['timed']}), identical={same}")
 
-    # ---- search leg --------------------------------------------------------
-    search = None
+    # ---- search ------------------------------------------------------------------
     if not args.no_search and w.Q.shape[0] > 0:
         Q = torch.from_numpy(w.Q).to(dev)
         k = spec.k
-        gt = exact_gt_u8(X, Q, k) if w.X.dtype == np.uint8 else exact_gt_f32(X, Q, k)
-        res = []
-        graphs = [("base", g, None)]
-        for o in range(0, len(outs), nr):
-            graphs.append((f"alpha={spec.sweep[o // nr][0]}/{spec.sweep[o // nr][1]}",
-                           g.derive(outs[o][0], outs[o][1]), None))
-        reach = {}
-        for name, gg, _ in graphs:
-            nb_, dg_ = (base_nbr, base_deg) if name == "base" else outs[
-                nr * [x[0] for x in graphs[1:]].index(name)]
-            reach[name] = reachable_fraction(nb_, dg_, w.start)
-            log(f"graph {name}: {100 * reach[name]:.2f}% of vertices reachable from the start")
+        gt = exact_gt_u8(X, Q, k) if esz == 1 else exact_gt_f32(X, Q, k)
+        res, reach = [], {}
+        graphs = [("base", g, base_nbr, base_deg)]
+        for ia, a in enumerate(spec.sweep):
+            o = outs[ia * nr]
+            graphs.append((f"alpha={a[0]}/{a[1]} R={spec.Rs[0]}", g.derive(o[0], o[1]), o[0], o[1]))
+        for gname, gg, nb_, dg_ in graphs:
+            reach[gname] = reachable_fraction(nb_, dg_, w.start)
             for L in spec.Ls:
                 gg.search(Q, k, L, want_dist=False)
                 torch.cuda.synchronize()
@@ -616,48 +724,167 @@ def main():
                     torch.cuda.synchronize()
                     lat.append(e0.elapsed_time(e1))
                 ms = float(np.median(lat))
-                rec = recall(ids, gt, k) if gt is not None else None
-                res.append({"graph": name, "L": L, "qps": Q.shape[0] / (ms * 1e-3),
-                            "batch_ms_p50": ms, "batch_ms_max": float(np.max(lat)),
-                            "recall_at_k": rec, "mean_hops": float(hops.float().mean().item())})
-                log(f"search {name} L={L}: {Q.shape[0] / (ms * 1e-3):.3e} QPS, recall {rec}")
-        search = {"k": k, "nq": int(Q.shape[0]), "reachable_fraction": reach, "results": res}
+                res.append({"graph": gname, "L": L, "qps": Q.shape[0] / (ms * 1e-3),
+                            "batch_ms_p50": ms, "recall_at_k": recall(ids, gt, k),
+                            "mean_hops": float(hops.float().mean().item())})
+        latency = latency_profile(g, Q, k, spec.Ls[0], stream)
+        if len(spec.Ls) > 1:
+            latency += latency_profile(g, Q, k, spec.Ls[-1], stream)
+        for gname, gg, _, _ in graphs[1:]:
+            gg.free()
+        rec["search"] = {"k": k, "nq": int(Q.shape[0]), "reachable_fraction": reach,
+                         "results": res, "latency_base_graph": latency,
+                         "frontier": frontier(res),
+                         "ground_truth": "exact integer (S, id)" if esz == 1 else
+                         "FP64 (S, id), see exact_gt_f32"}
+        for lt in latency:
+            log(f"search latency batch {lt['batch']} L={lt['L']}: p50 {lt['p50_ms']:.3f} ms, "
+                f"p99 {lt['p99_ms']:.3f} ms, {lt['qps']:.3e} QPS")
 
-    cpu = None
+    # ---- serving mix (headline workload) ------------------------------------------
+    if headline and not args.no_serve_leg and esz == 1:
+        rec["serving"] = serve_leg(g, w, spec, dev)
+
     if not args.no_cpu:
-        cpu = cpu_baseline(w, spec, args.cpu_budget)
-        log(f"cpu oracle: {cpu['value']:.1f} nodes/s ({cpu['sample']})")
+        rec["cpu_baseline"] = cpu_baseline(w, spec, args.cpu_budget if headline else
+                                           args.cpu_budget / 3)
+        log(f"cpu oracle: {rec['cpu_baseline']['value']:.1f} nodes/s "
+            f"({rec['cpu_baseline']['sample']})")
+    g.free()
+    g_knn.free()
+    del X, knn, base_nbr, base_deg, outs
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return rec
 
+
+def serve_leg(base_graph, w, spec, dev, n_req=400, rate=200.0):
+    """A short Poisson mix through the request loop on the headline graph (5%
+    prune requests at alpha in U{100..120}/100, R in {32, 48, 64}; 95% query
+    batches of log-uniform size 1..4096), batched and one-request-at-a-time
+    with the batched kernel."""
+    import torch
+
+    from paper_2602_08097_amd import Graph, Server
+
+    base = Graph(base_graph.points, base_graph.nbr, base_graph.deg, w.start)
+    Qpool = torch.from_numpy(w.Q).to(dev)
+    sspec = type(spec)(**{**spec.__dict__, "Rs": (32, 48, 64)})
+    trace = serve_trace(sspec, n_req, rate, 0, Qpool, dev, seed=1)
+    n = base.n
+    out = {"requests": n_req, "rate_req_s": rate, "graph": f"{spec.name} base"}
+    for mode, fifo in (("batched", 0), ("fifo", 1)):
+        server = Server(base, 6 * n * 65 * 4 + (1 << 20), n_streams=4, max_query_batch=8192,
+                        fifo=fifo)
+        r = serve_run(server, trace, Qpool, dev)
+        server.close()
+        torch.cuda.synchronize()
+        out[mode] = {k: v for k, v in r.items() if k != "stats"}
+        log(f"serving {mode}: query p50 {r['query']['p50_ms']:.2f} ms p99 "
+            f"{r['query']['p99_ms']:.2f} ms, prune p50 {r.get('prune', {}).get('p50_ms', 0):.1f} "
+            f"ms, {r['qps']:.3e} QPS")
+    base.free()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--configs", default=DEFAULT_CONFIGS,
+                    help="comma-separated workloads; the first is the headline (value)")
+    ap.add_argument("--config", default=None, help="a single workload (same as --configs X)")
+    ap.add_argument("--n", type=int, default=None)
+    ap.add_argument("--nq", type=int, default=None)
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-search", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-serve-leg", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="profiling run: a 256 MiB device copy for counter calibration, then "
+                         "the timed sweep only (no plain/search/CPU/serving legs)")
+    ap.add_argument("--cache", metavar="NPZ",
+                    help="load the generated workload from NPZ if present, else generate and save "
+                         "it there; '{config}' in the path is replaced by the workload name")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving benchmark: Poisson mix of prune requests and query batches "
+                         "through the request loop vs the one-at-a-time FIFO baseline")
+    ap.add_argument("--rates", default="100,200,400",
+                    help="serving: request arrival rates (requests/s)")
+    ap.add_argument("--requests", type=int, default=2000, help="serving: requests per rate")
+    ap.add_argument("--summarize-profile", metavar="DIR",
+                    help="summarise rocprofv3 output under DIR (trace and counter runs) into "
+                         "DIR/summary and exit")
+    ap.add_argument("--traffic-of", nargs=3, metavar=("KERNEL", "WORKLOAD", "N"),
+                    help="with --summarize-profile: write that kernel's calibrated traffic")
+    args = ap.parse_args()
+
+    if args.summarize_profile:
+        t = args.traffic_of
+        summarize_profile(args.summarize_profile, *(t[:2] if t else (None, None)),
+                          int(t[2]) if t else None)
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        sys.exit(2)
+    if args.serve:
+        serve_main(args)
+        return
+    if args.profile:
+        args.no_plain = args.no_search = args.no_cpu = args.no_serve_leg = True
+
+    import torch
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.profile:
+        # counter calibration: a plain device copy of a known size
+        # (a fill kernel writes COPY_BYTES; a reduction reads COPY_BYTES)
+        src = torch.randint(0, 255, (COPY_BYTES,), dtype=torch.uint8, device=dev)
+        for _ in range(3):
+            total = src.sum(dtype=torch.int64)
+        torch.cuda.synchronize()
+        del src, total
+    names = [args.config] if args.config else [c for c in args.configs.split(",") if c]
+    recs = {}
+    for i, name in enumerate(names):
+        recs[name] = run_config(name, args, dev, headline=(i == 0))
+    head = recs[names[0]]
     line = {
         "metric": METRIC,
-        "value": value,
+        "value": head["nodes_per_s"],
         "unit": "nodes/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": head["steps"],
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u8" if w.X.dtype == np.uint8 else "f32",
+        "dtype": head["dtype"],
         "data": "synthetic",
-        "config": {"workload": f"{spec.name}: {n} x {d} "
-                               f"{'uint8' if esz == 1 else 'float32'} Gaussian mixture, base "
-                               f"exact {spec.knn_k}-NN + RobustPrune alpha={spec.base_alpha[0]}/"
-                               f"{spec.base_alpha[1]} R={spec.base_R}; sweep alpha="
-                               f"{[f'{a}/{b}' for a, b in spec.sweep]} R={list(spec.Rs)}",
-                   "n": n, "d": d, "mean_base_degree": float(deg_np.mean()),
-                   "rechecks_per_node_alpha": ctr["rechecks"] / max(1, ctr["nodes"]),
-                   "vertices_per_workgroup": tune["waves"],
-                   "outputs_per_step": len(outs)},
-        "roofline": roofline,
-        "mfma": mfma,
-        "distance_error": gram_err if gram_err is not None else
-        ({"max_rel": 0.0, "mean_rel": 0.0, "note": "uint8: exact int32 distances"}
-         if w.X.dtype == np.uint8 else None),
-        "cpu_baseline": cpu,
-        "plain": plain,
-        "search": search,
+        "config": {"workload": f"{names[0]}: {head['n']} x {head['d']} "
+                               f"{'uint8' if head['dtype'] == 'u8' else 'float32'} Gaussian "
+                               f"mixture, base graph = RobustPrune of exact K-NN lists; sweep "
+                               f"alpha={head['sweep']['alphas']} R={head['sweep']['Rs']}",
+                   "n": head["n"], "d": head["d"],
+                   "outputs_per_step": len(head["sweep"]["alphas"]) * len(head["sweep"]["Rs"])},
+        "roofline": head["roofline"],
+        "cpu_baseline": head.get("cpu_baseline"),
+        "node_prunes_per_s": head["node_prunes_per_s"],
+        "input_edges_per_s": head["input_edges_per_s"],
+        "output_edges_per_s": head["output_edges_per_s"],
+        "mfma": head["mfma"],
+        "plain": head.get("plain"),
+        "search": head.get("search"),
+        "serving": head.get("serving"),
+        "headline": {k: v for k, v in head.items()
+                     if k not in ("roofline", "cpu_baseline", "mfma", "plain", "search",
+                                  "serving")},
+        "configs": {k: v for k, v in recs.items() if k != names[0]},
     }
     print(json.dumps(line), flush=True)
 
