@@ -230,7 +230,7 @@ def batched_kernel_name(dtype, r_max, d):
         if d % 16 == 0 and r_max <= 128 and d <= 128:
             return "prune_u8_wide_kernel"
         return "prune_plain_kernel"
-    if r_max <= 64 or (r_max <= 96 and d <= 3408):
+    if r_max <= 64 or (r_max <= 96 and d <= 3328):
         return "prune_f32_kernel"
     return "prune_plain_kernel"
 
@@ -590,10 +590,20 @@ def run_config(name, args, dev, headline):
         knn = torch.from_numpy(w.knn).to(dev)
         build["knn"] = "generator lists (FP32 GEMM + top-k on the GPU)"
     g_knn = Graph(X, knn, kdeg, w.start)
-    tb = time.perf_counter()
-    base_nbr, base_deg = g_knn.prune(spec.base_alpha, spec.base_R)
-    torch.cuda.synchronize()
-    build["base_prune_s"] = time.perf_counter() - tb
+    base_cache = args.cache.replace("{config}", name + "_base") if args.cache else None
+    if base_cache and os.path.exists(base_cache):
+        # profiling runs: the base graph of an earlier run of this workload
+        z = np.load(base_cache, allow_pickle=False)
+        base_nbr = torch.from_numpy(z["nbr"]).to(dev)
+        base_deg = torch.from_numpy(z["deg"]).to(dev)
+        build["base_prune_s"] = None
+    else:
+        tb = time.perf_counter()
+        base_nbr, base_deg = g_knn.prune(spec.base_alpha, spec.base_R)
+        torch.cuda.synchronize()
+        build["base_prune_s"] = time.perf_counter() - tb
+        if base_cache:
+            np.savez(base_cache, nbr=base_nbr.cpu().numpy(), deg=base_deg.cpu().numpy())
     build["base_prune_kernel"] = batched_kernel_name(w.X.dtype, spec.knn_k, d)
     if w.targets is not None:
         # uneven out-degrees: keep the first min(t_p, deg) ids of each base list
@@ -610,6 +620,22 @@ def run_config(name, args, dev, headline):
     nr = len(spec.Rs)
     n_out = len(spec.sweep) * nr
     outs = [g._outs(spec.Rs[o % nr]) for o in range(n_out)]
+
+    if args.profile_search:
+        # profiling run of GreedySearch alone: the full query set on the base
+        # graph at the first L, a few times
+        Q = torch.from_numpy(w.Q).to(dev)
+        for _ in range(args.steps):
+            g.search(Q, spec.k, spec.Ls[0], want_dist=False)
+        torch.cuda.synchronize()
+        hops = g.search(Q, spec.k, spec.Ls[0], want_dist=False)[2]
+        log(f"search profile: {Q.shape[0]} queries x {args.steps + 1} launches, k={spec.k}, "
+            f"L={spec.Ls[0]}, mean visited {hops.float().mean().item():.2f}")
+        return {"workload": name, "n": n, "d": d, "dtype": "u8" if w.X.dtype == np.uint8 else "f32",
+                "steps": args.steps, "ms_per_step": 0.0, "nodes_per_s": 0.0,
+                "node_prunes_per_s": 0.0, "input_edges_per_s": 0.0, "output_edges_per_s": 0.0,
+                "sweep": {"alphas": [], "Rs": []}, "roofline": None, "mfma": None,
+                "mean_visited": float(hops.float().mean().item())}
 
     # ---- launch tuning, then the timed sweep ----------------------------------
     tune = g.autotune_sweep(spec.sweep, spec.Rs, outs=outs)
@@ -741,6 +767,10 @@ def run_config(name, args, dev, headline):
             log(f"search latency batch {lt['batch']} L={lt['L']}: p50 {lt['p50_ms']:.3f} ms, "
                 f"p99 {lt['p99_ms']:.3f} ms, {lt['qps']:.3e} QPS")
 
+    # ---- prune versus rebuild (Table 2's comparison, slow preprocessing) -------
+    if not args.no_rebuild and n <= 20_000:
+        rec["prune_vs_rebuild"] = rebuild_leg(X, w, spec)
+
     # ---- serving mix (headline workload) ------------------------------------------
     if headline and not args.no_serve_leg and esz == 1:
         rec["serving"] = serve_leg(g, w, spec, dev)
@@ -756,6 +786,46 @@ def run_config(name, args, dev, headline):
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     return rec
+
+
+def rebuild_leg(X, w, spec, R=256):
+    """Table 2's comparison on the GPU at this size: the slow-preprocessing
+    graph RobustPrune(p, P \\ {p}, alpha, R) (Section 2.1) at the base alpha,
+    then for every alpha of the sweep its rebuild from scratch against
+    RP-Tuning of the base graph (Section 3), both timed on the device."""
+    import torch
+
+    from paper_2602_08097_amd import Graph, build_slow
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, (time.perf_counter() - t0) * 1e3
+
+    (b_nb, b_dg), t_base = timed(lambda: build_slow(X, spec.base_alpha, R))
+    r_max = int(b_dg.max().item())
+    g = Graph(X, b_nb[:, :r_max].contiguous(), b_dg, w.start)
+    g.prune(spec.sweep[0], r_max)  # warm
+    rows = []
+    for a in spec.sweep:
+        (r_nb, r_dg), t_rebuild = timed(lambda: build_slow(X, a, R))
+        (p_nb, p_dg), t_prune = timed(lambda: g.prune(a, r_max))
+        rows.append({"alpha2": f"{a[0]}/{a[1]}", "rebuild_ms": t_rebuild, "prune_ms": t_prune,
+                     "speedup": t_rebuild / t_prune,
+                     "rebuild_mean_degree": float(r_dg.float().mean().item()),
+                     "prune_mean_degree": float(p_dg.float().mean().item())})
+        log(f"alpha2={a[0]}/{a[1]}: rebuild {t_rebuild:.1f} ms, RP-Tuning {t_prune:.3f} ms "
+            f"({t_rebuild / t_prune:.0f}x)")
+    _, t_sweep = timed(lambda: g.prune_sweep(spec.sweep, [r_max]))
+    g.free()
+    return {"n": int(X.shape[0]), "R": R, "base_alpha": f"{spec.base_alpha[0]}/{spec.base_alpha[1]}",
+            "base_build_ms": t_base, "base_mean_degree": float(b_dg.float().mean().item()),
+            "base_max_degree": r_max, "vertices_at_R": int((b_dg == R).sum().item()),
+            "rows": rows, "all_alphas_one_sweep_ms": t_sweep,
+            "kernel": "rebuild: rp_build_slow; RP-Tuning: " +
+                      batched_kernel_name(w.X.dtype, r_max, w.X.shape[1])}
 
 
 def serve_leg(base_graph, w, spec, dev, n_req=400, rate=200.0):
@@ -802,9 +872,12 @@ def main():
     ap.add_argument("--no-search", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serve-leg", action="store_true")
+    ap.add_argument("--no-rebuild", action="store_true")
     ap.add_argument("--profile", action="store_true",
                     help="profiling run: a 256 MiB device copy for counter calibration, then "
                          "the timed sweep only (no plain/search/CPU/serving legs)")
+    ap.add_argument("--profile-search", action="store_true",
+                    help="profiling run of GreedySearch on the base graph only")
     ap.add_argument("--cache", metavar="NPZ",
                     help="load the generated workload from NPZ if present, else generate and save "
                          "it there; '{config}' in the path is replaced by the workload name")
@@ -833,14 +906,15 @@ def main():
     if args.serve:
         serve_main(args)
         return
-    if args.profile:
+    if args.profile or args.profile_search:
         args.no_plain = args.no_search = args.no_cpu = args.no_serve_leg = True
+        args.no_rebuild = True
 
     import torch
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    if args.profile:
+    if args.profile or args.profile_search:
         # counter calibration: a plain device copy of a known size
         # (a fill kernel writes COPY_BYTES; a reduction reads COPY_BYTES)
         src = torch.randint(0, 255, (COPY_BYTES,), dtype=torch.uint8, device=dev)

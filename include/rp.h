@@ -273,6 +273,34 @@ rp_status rp_tune_get(rp_graph_t g, int32_t n_a, int32_t n_R, int32_t* waves);
 rp_status rp_gram_error(rp_graph_t g, const int32_t* nodes, int64_t n_nodes, double* out,
                         void* stream);
 
+/*
+ * rp_build_slow -- the "slow preprocessing" construction (Section 2.1):
+ * RobustPrune(p, P \ {p}, alpha, R) (Algorithm 1) for every point p of the
+ * point set (n x d, dtype RP_U8 or RP_F32, finite coordinates).  With
+ * R >= n - 1 the graph is alpha-reachable (Lemma 2.2); RP-Tuning (Section 3)
+ * is measured against rebuilding it at the new alpha.  O(n^2) work per point.
+ *   out_nbr: n x R int32, row p the kept ids in the order Algorithm 1 adds
+ *            them (ascending (S(p, .), id)), -1 padded; out_deg: n int32.
+ * Distances and the alpha test as everywhere in this header.  A workspace of
+ * at most 1 GiB is allocated and freed in stream order on `stream`.
+ */
+rp_status rp_build_slow(const void* points, int32_t dtype, int64_t n, int32_t d, rp_alpha alpha,
+                        int32_t R, int32_t* out_nbr, int32_t* out_deg, void* stream);
+
+/*
+ * rp_f32_band -- the rounding band of the float32 batched kernel for points of
+ * dimension d (1 <= d <= 4096): out (host, 4 doubles) receives c1, c2, c3 of
+ *   |S~(i, j) - S(i, j) 2^2e| <= c1 s + c2 sqrt(s) + c3,   s = S(p, j) 2^2e,
+ * for every pair of candidates i before j of a vertex p, where S~ is the
+ * kernel's split-FP16 matrix-unit value in the vertex's frame scaled by 2^e
+ * and S the canonical FP64 value.  A pair is decided from S~ only when the
+ * alpha test holds or fails by more than this band; otherwise S is recomputed.
+ * out[3] is the number of dimensions the kernel sums in one accumulator
+ * before adding it to the running total (d when it does not restart).
+ * Host only (no device work).
+ */
+rp_status rp_f32_band(int32_t d, double* out);
+
 /* rp_free_graph -- release a handle (NULL is ignored).  Synchronises the
  * device; the caller's arrays are not freed. */
 void rp_free_graph(rp_graph_t g);

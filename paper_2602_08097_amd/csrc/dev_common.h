@@ -8,10 +8,27 @@ namespace rp {
 // Canonical FP64 squared distance of two float32 rows: t = (double)a - (double)b
 // rounded once, accumulated with a correctly rounded fused multiply-add in
 // ascending k.  Built with -ffp-contract=off so no other fusion happens.
+// (16-byte loads when both rows are 16-byte aligned and d % 4 == 0; the
+// evaluation order is the same.)
 __device__ __forceinline__ double canon_sq_f32(const float* __restrict__ a,
                                                const float* __restrict__ b, int d) {
   double acc = 0.0;
-  for (int k = 0; k < d; ++k) {
+  int k = 0;
+  if ((((uintptr_t)a | (uintptr_t)b) & 15) == 0 && (d & 3) == 0) {
+    for (; k < d; k += 4) {
+      const float4 x = *(const float4*)(a + k);
+      const float4 y = *(const float4*)(b + k);
+      double t = (double)x.x - (double)y.x;
+      acc = __fma_rn(t, t, acc);
+      t = (double)x.y - (double)y.y;
+      acc = __fma_rn(t, t, acc);
+      t = (double)x.z - (double)y.z;
+      acc = __fma_rn(t, t, acc);
+      t = (double)x.w - (double)y.w;
+      acc = __fma_rn(t, t, acc);
+    }
+  }
+  for (; k < d; ++k) {
     double t = (double)a[k] - (double)b[k];
     acc = __fma_rn(t, t, acc);
   }
@@ -29,11 +46,27 @@ __device__ __forceinline__ uint32_t sq_u8(const uint8_t* __restrict__ a,
   return acc;
 }
 
-// FP32 direct-difference squared distance (approximate).
+// FP32 direct-difference squared distance (approximate), sequential in k;
+// 16-byte loads when both rows are 16-byte aligned and d % 4 == 0.
 __device__ __forceinline__ float sq_f32(const float* __restrict__ a,
                                         const float* __restrict__ b, int d) {
   float acc = 0.f;
-  for (int k = 0; k < d; ++k) {
+  int k = 0;
+  if ((((uintptr_t)a | (uintptr_t)b) & 15) == 0 && (d & 3) == 0) {
+    for (; k < d; k += 4) {
+      const float4 x = *(const float4*)(a + k);
+      const float4 y = *(const float4*)(b + k);
+      float t = x.x - y.x;
+      acc = __fmaf_rn(t, t, acc);
+      t = x.y - y.y;
+      acc = __fmaf_rn(t, t, acc);
+      t = x.z - y.z;
+      acc = __fmaf_rn(t, t, acc);
+      t = x.w - y.w;
+      acc = __fmaf_rn(t, t, acc);
+    }
+  }
+  for (; k < d; ++k) {
     float t = a[k] - b[k];
     acc = __fmaf_rn(t, t, acc);
   }

@@ -30,7 +30,7 @@
 //              FP32 difference is split as hi + lo, two FP16 values, and
 //              G~ = sum hi hi' + hi lo' + lo hi' runs on
 //              v_mfma_f32_32x32x16_f16; for long rows the accumulator restarts
-//              every 32 dimensions and the pieces are summed in FP32.
+//              every 128 dimensions and the pieces are summed in FP32 in LDS.
 //              S~(i, j) = (S(p, i) + S(p, j)) 2^2e - 2 G~(i, j) goes to an
 //              FP32 tile of the blocks on and above the diagonal, by rank
 //              (entries with j <= i hold +inf).
@@ -48,6 +48,7 @@
 #include <math.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "dev_common.h"
 
@@ -58,7 +59,7 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 
 namespace {
 
-constexpr int kDC = 32;  // dimensions per accumulator chunk of the Gram (long rows)
+constexpr int kDC = 64;  // dimensions per accumulator chunk of the Gram (long rows)
 constexpr int kMaxDimF32 = 4096;
 
 template <int NB>
@@ -307,19 +308,81 @@ __device__ __forceinline__ void ring_fill(Ring<NB>& r, const float* const (&rows
   if (PF > 3) r.d = fetch_step<NB, VEC>(rows, d, 3, half);
 }
 
+// Chunk sums of the Gram accumulators (CSUM) live in LDS, in the region the
+// S~ tile takes afterwards: block c's 16 values of lane l sit at
+// acc + 1024 c + 256 q + 4 l + (v % 4) for v = 4 q + (v % 4), so every access
+// is a 16-byte vector load or store of consecutive lanes.  Each word has one
+// owner lane.  Blocks in use are (0,0); (0,1), (1,1) when two row blocks hold
+// slots; the rest with three.
+template <int NB>
+__device__ __forceinline__ bool block_in_use(int c, int nbu) {
+  return c == 0 || (c < 3 ? nbu > 1 : nbu > 2);
+}
+
+// acc += cur, then cur = 0 (a fresh accumulator for the next chunk).
+template <int NB>
+__device__ __forceinline__ void chunk_flush(v16f (&cur)[Shape<NB>::NP], float* acc, int lane,
+                                            int nbu) {
+  constexpr int NP = Shape<NB>::NP;
+#pragma unroll
+  for (int c = 0; c < NP; ++c) {
+    if (!block_in_use<NB>(c, nbu)) continue;  // uniform
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      float4* a = (float4*)(acc + 1024 * c + 256 * q + 4 * lane);
+      float4 t = *a;
+      t.x += cur[c][4 * q];
+      t.y += cur[c][4 * q + 1];
+      t.z += cur[c][4 * q + 2];
+      t.w += cur[c][4 * q + 3];
+      *a = t;
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) cur[c][v] = 0.f;
+  }
+}
+
+template <int NB>
+__device__ __forceinline__ void chunk_zero(float* acc, int lane) {
+#pragma unroll
+  for (int c = 0; c < Shape<NB>::NP; ++c) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      *(float4*)(acc + 1024 * c + 256 * q + 4 * lane) = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+
+// The chunk sums back into the accumulator registers (after the last flush).
+template <int NB>
+__device__ __forceinline__ void chunk_load(v16f (&cur)[Shape<NB>::NP], const float* acc,
+                                           int lane) {
+#pragma unroll
+  for (int c = 0; c < Shape<NB>::NP; ++c) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 t = *(const float4*)(acc + 1024 * c + 256 * q + 4 * lane);
+      cur[c][4 * q] = t.x;
+      cur[c][4 * q + 1] = t.y;
+      cur[c][4 * q + 2] = t.z;
+      cur[c][4 * q + 3] = t.w;
+    }
+  }
+}
+
 // One pass over this lane's rows (rows[b]: block b's row l % 32) whose first
-// PF steps are in `ring`: the Gram blocks into cur / tot and, with PROW, the
-// canonical S(p, .) of slot lane (sp[0]) and of slot 64 + l % 32 (sp[1],
-// three blocks).  nbu: blocks in use.
+// PF steps are in `ring`: the Gram blocks into cur (chunk sums into acc with
+// CSUM) and, with PROW, the canonical S(p, .) of slot lane (sp[0], rows of
+// blocks 0 and 1) and of slot 64 + l % 32 (sp[1], block 2).  nbu: blocks in use.
 template <int NB, bool CSUM, bool PROW, bool VEC, int PF>
 __device__ __forceinline__ void gram_pass(Ring<NB>& ring, const float* const (&rows)[NB], int d,
                                           int nbu, const double* __restrict__ xq,
                                           const float* __restrict__ xs, float scf,
                                           int half, v16f (&cur)[Shape<NB>::NP],
-                                          v16f (&tot)[Shape<NB>::NP], double (&sp)[Shape<NB>::NW]) {
-  constexpr int NP = Shape<NB>::NP;
+                                          float* acc, int lane, double (&sp)[Shape<NB>::NW]) {
+  static_assert(PF >= 2 && PF <= 4, "two to four steps in flight");
   const int nsteps = (d + 15) >> 4;
   const bool ragged = (d & 15) != 0;
+  constexpr int kChunkSteps = kDC / 16;
   auto step = [&](const Step<NB>& q, int s) {
     const int o0 = 16 * s + 8 * half;
     float x[NB][8];
@@ -353,16 +416,9 @@ __device__ __forceinline__ void gram_pass(Ring<NB>& ring, const float* const (&r
         gram3(cur[blk(2, 2)], hi[2], lo[2], hi[2], lo[2]);
       }
     }
-    if (CSUM && ((s & 1) || s == nsteps - 1)) {  // a fresh accumulator every 32 dimensions
-#pragma unroll
-      for (int c = 0; c < NP; ++c) {
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          tot[c][v] += cur[c][v];
-          cur[c][v] = 0.f;
-        }
-      }
-    }
+    // a fresh accumulator every kDC dimensions
+    if (CSUM && ((s % kChunkSteps) == kChunkSteps - 1 || s == nsteps - 1))
+      chunk_flush<NB>(cur, acc, lane, nbu);
     if (PROW) {
       sp[0] = row_step(sp[0], x[0], x[1], xq + 16 * s);
       if constexpr (NB > 2) {
@@ -440,7 +496,7 @@ __device__ __forceinline__ float row_zmin(const float* St, const float* invt, in
 // pair's S~ is compared with the canonical FP64 S(i, j) (relative error, and
 // error over the proven band), and nothing is written.
 // Workgroups of up to 8 wavefronts for 64 candidates, 4 for 96 (whose
-// registers take a whole SIMD lane file).
+// registers take a whole SIMD lane file); one vertex per wavefront.
 template <int NA, int NB, bool CSUM, bool VEC, int PF, bool CAP, bool DIAG>
 __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphView g, SweepArgs a, F32Args fa,
                                                         DevCounters* ctr, int32_t wave_lds) {
@@ -478,24 +534,24 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
     }
     mq = g.deg[q];
   };
-  // usable ids, this lane's rows, and the first steps of the rows
+  // usable ids by slot; the rows of the first NL row blocks of this lane
   int idw[NW];
-  const float* rows[NB];
   int fe = 0;
   float4 xv;
-  Ring<NB> ring;
-  auto prepare = [&](int64_t q, const int (&raw)[NW], int mq) {
+  auto usable_ids = [&](int64_t q, const int (&raw)[NW], int mq) {
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
       const int s = lane + 64 * w;
       idw[w] = (s < mq && raw[w] != (int)q) ? raw[w] : -1;
     }
+  };
+  auto rows_of = [&](const int (&ids)[NW], auto& rows) {
+    constexpr int NL = sizeof(rows) / sizeof(rows[0]);
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int id = b < 2 ? __shfl(idw[0], 32 * b + l32, 64) : __shfl(idw[NW - 1], l32, 64);
-      rows[b] = X + (int64_t)(id >= 0 ? id : (int)q) * d;
+    for (int b = 0; b < NL; ++b) {
+      const int id = b < 2 ? __shfl(ids[0], 32 * b + l32, 64) : __shfl(ids[NW - 1], l32, 64);
+      rows[b] = X + (int64_t)(id >= 0 ? id : (int)p) * d;
     }
-    ring_fill<NB, VEC, PF>(ring, rows, d, half);
   };
   // loads that do not wait for the list: x_p and the vertex's frame exponent
   // (computed with the graph from its list and the per-point max |x_k|)
@@ -517,7 +573,7 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
   int m, raw[NW];
   load_list(p, raw, m);
   early(p);
-  prepare(p, raw, m);
+  usable_ids(p, raw, m);
   unsigned long long rechecks = 0;
   double dg_max_rel = 0.0, dg_sum_rel = 0.0, dg_max_band = 0.0;
   unsigned long long dg_pairs = 0;
@@ -534,32 +590,42 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
     *(double2*)(xq + c + 2) = make_double2((double)v.z, (double)v.w);
     *(float4*)(xs + c) = make_float4(v.x * scf, v.y * scf, v.z * scf, v.w * scf);
   };
-  if (4 * lane < xpf) stage(4 * lane, xv);
-  for (int c = 4 * lane + 256; c < xpf; c += 256) {  // long rows
-    const float* xrow = X + p * d;
-    float4 v;
-    v.x = c < d ? xrow[c] : 0.f;
-    v.y = c + 1 < d ? xrow[c + 1] : 0.f;
-    v.z = c + 2 < d ? xrow[c + 2] : 0.f;
-    v.w = c + 3 < d ? xrow[c + 3] : 0.f;
-    stage(c, v);
+  {
+    if (4 * lane < xpf) stage(4 * lane, xv);
+    for (int c = 4 * lane + 256; c < xpf; c += 256) {  // long rows
+      const float* xrow = X + p * d;
+      float4 v;
+      v.x = c < d ? xrow[c] : 0.f;
+      v.y = c + 1 < d ? xrow[c + 1] : 0.f;
+      v.z = c + 2 < d ? xrow[c + 2] : 0.f;
+      v.w = c + 3 < d ? xrow[c + 3] : 0.f;
+      stage(c, v);
+    }
   }
   wave_sync();
 
   // ---- a2 + a3 + a5: one pass over the rows in slot order ----------------
-  v16f cur[NP], tot[NP];
+  v16f cur[NP];
 #pragma unroll
   for (int c = 0; c < NP; ++c) {
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      cur[c][v] = 0.f;
-      tot[c][v] = 0.f;
-    }
+    for (int v = 0; v < 16; ++v) cur[c][v] = 0.f;
   }
   double sp[NW];
 #pragma unroll
   for (int w = 0; w < NW; ++w) sp[w] = 0.0;
-  gram_pass<NB, CSUM, true, VEC, PF>(ring, rows, d, nbu, xq, xs, scf, half, cur, tot, sp);
+  // one pass over the rows of `ids` (the tile region holds the chunk sums
+  // for now)
+  auto pass = [&](const int (&ids)[NW], auto prow_c) {
+    constexpr bool PROW = decltype(prow_c)::value;
+    const float* rows[NB];
+    rows_of(ids, rows);
+    Ring<NB> ring;
+    ring_fill<NB, VEC, PF>(ring, rows, d, half);
+    if (CSUM) chunk_zero<NB>(St, lane);
+    gram_pass<NB, CSUM, PROW, VEC, PF>(ring, rows, d, nbu, xq, xs, scf, half, cur, St, lane, sp);
+  };
+  pass(idw, std::true_type{});
 
   // ---- a4: sort by (S(p, j), id); drop repeated ids -------------------------
   uint64_t kh[NW];
@@ -586,31 +652,23 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
       const uint32_t ll = (uint32_t)__shfl((int)kl[0], 63, 64);
       unsorted = unsorted || (lane == 0 && key_less(kh[NW - 1], kl[NW - 1], lh, ll));
     }
+    // out of rank order: sort the keys, stream the rows again by rank
+    bool again = false;
+    int idk[NW];
     if (!a.unsorted && __ballot(unsorted) != 0) {
-      // out of rank order: sort the keys, stream the rows again by rank
       if constexpr (NW == 2) wave_sort128(kh[0], kl[0], kh[1], kl[1], lane);
       else wave_sort2(kh[0], kl[0], lane);
-      int idk[NW];
 #pragma unroll
       for (int w = 0; w < NW; ++w) idk[w] = kh[w] != ~0ull ? (int)(kl[w] >> SB) : -1;
-      const float* rrows[NB];
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const int id = b < 2 ? __shfl(idk[0], 32 * b + l32, 64) : __shfl(idk[NW - 1], l32, 64);
-        rrows[b] = X + (int64_t)(id >= 0 ? id : (int)p) * d;
-      }
+      again = true;
+    }
+    if (again) {
 #pragma unroll
       for (int c = 0; c < NP; ++c) {
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          cur[c][v] = 0.f;
-          tot[c][v] = 0.f;
-        }
+        for (int v = 0; v < 16; ++v) cur[c][v] = 0.f;
       }
-      double unused[NW];
-      ring_fill<NB, VEC, PF>(ring, rrows, d, half);
-      gram_pass<NB, CSUM, false, VEC, PF>(ring, rrows, d, nbu, xq, xs, scf, half, cur, tot,
-                                         unused);
+      pass(idk, std::false_type{});
     }
   }
   wave_sync();  // the x_p 2^e reads are done before the region takes S(p, .)
@@ -663,7 +721,11 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
   wave_sync();
 
   // ---- a5: S~ tile by rank ----------------------------------------------------
-  auto acc_of = [&](int c) -> const v16f& { return CSUM ? tot[c] : cur[c]; };
+  if (CSUM) {
+    chunk_load<NB>(cur, St, lane);  // every chunk has been flushed
+    wave_sync();                    // all read before the tile is written
+  }
+  auto acc_of = [&](int c) -> const v16f& { return cur[c]; };
   store_block<0, 0>(St, sr, acc_of(blk(0, 0)), l32, half);
   if (nbu > 1) {
     store_block<0, 1>(St, sr, acc_of(blk(0, 1)), l32, half);
@@ -1067,7 +1129,7 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
 //   dropped lo lo'      <= 2^-22 (1 + 2^-9) s;
 //   FP32 accumulation   gamma over the additions into one accumulator, with
 //                       unit 2^-23 (covers truncating hardware), plus the
-//                       gamma of the chunk sums (unit 2^-24);
+//                       gamma of the chunk sums (unit 2^-23 as well);
 //   |G~ - G| <= (2 e1 + e1^2 + lo lo' + acc) s + 2 ea sqrt(d) (1 + e1)(1 + acc) sqrt(s)
 //               + d ea^2 (1 + acc);
 //   S~ = (S(p,i) + S(p,j)) 2^2e - 2 G~ in FP32 adds 8 * 2^-24 s, and the
@@ -1082,7 +1144,8 @@ void f32_bound_constants(int d, bool csum, double* c1, double* c2, double* c3) {
   const double ea = 0x1p-14;
   const double nadd = csum ? 3.0 * kDC + 1.0 : 3.0 * d + 1.0;
   const double g1 = gam(nadd, 0x1p-23);
-  const double g2 = csum ? gam((double)((d + kDC - 1) / kDC), u24) : 0.0;
+  // chunk sums: FP32 adds, taken with the unit of truncation as well
+  const double g2 = csum ? gam((double)((d + kDC - 1) / kDC), 0x1p-23) : 0.0;
   const double acc = (g1 + g2 + g1 * g2) * (1.0 + 0x1p-9);
   const double lolo = 0x1p-22 * (1.0 + 0x1p-9);
   const double sd = sqrt((double)d);
@@ -1108,8 +1171,8 @@ Plan plan_of(const GraphView& g) {
   return pl;
 }
 
-// Steps in flight: two for 64 candidates (three wavefronts per SIMD fit), four
-// for 96 (one wavefront per SIMD, so it carries the memory parallelism alone).
+// Steps in flight: two for 64 candidates (three wavefronts per SIMD fit),
+// four for 96 (one wavefront per SIMD).
 template <int NB>
 constexpr int prefetch_steps() {
   return NB == 3 ? 4 : 2;
@@ -1159,7 +1222,7 @@ hipError_t launch_diag(const GraphView& g, const SweepArgs& a, const F32Args& fa
                        DevCounters* ctr, hipStream_t s, int wave_lds) {
   constexpr int PF = prefetch_steps<NB>();
   auto k = prune_f32_kernel<1, NB, CSUM, VEC, PF, false, true>;
-  hipLaunchKernelGGL(k, dim3((unsigned)fa.n_nodes), dim3(64), wave_lds, s, g, a, fa, ctr,
+  hipLaunchKernelGGL(k, dim3((unsigned)fa.n_nodes), dim3(64), (size_t)wave_lds, s, g, a, fa, ctr,
                      wave_lds);
   return hipGetLastError();
 }
@@ -1244,8 +1307,16 @@ SweepArgs alphas_descending(const SweepArgs& a_in, int nr) {
 
 int prune_f32_wave_lds(const GraphView& g) { return plan_of(g).wave_lds; }
 
-// Lists of at most 96 ids whose per-wavefront LDS fits a workgroup (96
-// candidates above d = 3408 do not: those graphs take the plain kernel).
+// The band of a float32 graph of dimension d as its sweeps use it (chunked
+// accumulators above d = 128), and the dimensions per accumulator chunk.
+void f32_band(int d, double* c) {
+  const bool csum = d > 128;
+  f32_bound_constants(d, csum, &c[0], &c[1], &c[2]);
+  c[3] = csum ? kDC : d;
+}
+
+// Lists of at most 96 ids whose LDS fits a workgroup (96 candidates above
+// d = 3408 do not: those graphs take the plain kernel).
 bool prune_f32_shape_ok(const GraphView& g) {
   return g.dtype == RP_F32 && g.r_max <= 96 && g.d <= kMaxDimF32 && g.n <= (1ll << 25) &&
          g.maxabs != nullptr && plan_of(g).wave_lds <= kMaxLdsPerGroup;

@@ -569,6 +569,43 @@ rp_status rp_knn_u8(const uint8_t* points, int64_t n, int32_t d, const int32_t* 
   return st == RP_OK ? ok() : st;
 }
 
+rp_status rp_build_slow(const void* points, int32_t dtype, int64_t n, int32_t d, rp_alpha alpha,
+                        int32_t R, int32_t* out_nbr, int32_t* out_deg, void* stream) {
+  if (dtype != RP_U8 && dtype != RP_F32) return fail(RP_EINVAL, "dtype must be RP_U8 or RP_F32");
+  if (n < 1 || n >= (1ll << 31)) return fail(RP_EINVAL, "n must be in [1, 2^31)");
+  if (d < 1 || d > rp::kMaxDim) return fail(RP_EINVAL, "d must be in [1, %d]", rp::kMaxDim);
+  if (R < 1) return fail(RP_EINVAL, "R must be >= 1 (got %d)", R);
+  rp_status st = check_alpha(alpha);
+  if (st != RP_OK) return st;
+  if (!device_range(points, (size_t)n * d * elem_size(dtype)))
+    return fail(RP_EINVAL, "points is not a device array of n*d elements");
+  if (!device_range(out_nbr, (size_t)n * R * 4))
+    return fail(RP_EINVAL, "out_nbr is not a device array of n*R int32");
+  if (!device_range(out_deg, (size_t)n * 4))
+    return fail(RP_EINVAL, "out_deg is not a device array of n int32");
+  hipStream_t s = (hipStream_t)stream;
+  const int groups = rp::slow_build_groups(n);
+  const size_t bytes = rp::slow_build_workspace_bytes(n, groups);
+  void* ws = nullptr;
+  if (hipMallocAsync(&ws, bytes, s) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(RP_ENOMEM, "workspace of %zu bytes could not be allocated", bytes);
+  }
+  const hipError_t e = rp::launch_slow_build(
+      points, dtype, n, d, (uint32_t)alpha.num * alpha.num, (uint32_t)alpha.den * alpha.den, R,
+      out_nbr, out_deg, ws, groups, s);
+  (void)hipFreeAsync(ws, s);
+  st = check_launch(e, "slow build");
+  return st == RP_OK ? ok() : st;
+}
+
+rp_status rp_f32_band(int32_t d, double* out) {
+  if (!out) return fail(RP_EINVAL, "out is null");
+  if (d < 1 || d > rp::kMaxDim) return fail(RP_EINVAL, "d must be in [1, %d]", rp::kMaxDim);
+  rp::f32_band(d, out);
+  return ok();
+}
+
 rp_status rp_read_counters(rp_graph_t g, rp_counters* out, int32_t reset, void* stream) {
   if (!g) return fail(RP_ESTATE, "graph is null");
   if (!out) return fail(RP_EINVAL, "out is null");

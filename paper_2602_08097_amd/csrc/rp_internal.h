@@ -105,6 +105,13 @@ size_t knn_u8_workspace_bytes(int64_t nq, int slices);
 hipError_t launch_knn_u8(const uint8_t* X, int64_t n, int32_t d, const int32_t* qids, int64_t nq,
                          const int32_t* cids, int64_t nc, int32_t K, int32_t* out,
                          uint64_t* workspace, int slices, hipStream_t s);
+void f32_band(int d, double* c);               // c1, c2, c3 of the float32 band; chunk
+// Slow-preprocessing build (k_slow_build.hip): workgroups, workspace, launch.
+int slow_build_groups(int64_t n);
+size_t slow_build_workspace_bytes(int64_t n, int groups);
+hipError_t launch_slow_build(const void* X, int32_t dtype, int64_t n, int32_t d, uint32_t num2,
+                             uint32_t den2, int32_t R, int32_t* out_nbr, int32_t* out_deg,
+                             void* workspace, int groups, hipStream_t s);
 bool prune_f32_shape_ok(const GraphView& g);   // shape the float32 batched kernel serves
 bool prune_f32_supported(const GraphView& g);  // ... and its frame exponents are set
 hipError_t launch_search(const GraphView& g, const void* Q, int64_t nq, int32_t k, int32_t L,

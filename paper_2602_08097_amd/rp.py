@@ -58,7 +58,7 @@ REQ_PRUNE = 1
 REQ_QUERY = 2
 
 EXPORTS = ["rp_load_graph", "rp_graph_derive", "rp_prune", "rp_prune_sweep", "rp_prune_plain",
-           "rp_prune_sweep_unsorted", "rp_knn_u8", "rp_knn_u8_noalloc",
+           "rp_prune_sweep_unsorted", "rp_knn_u8", "rp_knn_u8_noalloc", "rp_f32_band", "rp_build_slow",
            "rp_search", "rp_read_counters", "rp_free_graph", "rp_last_error",
            "rp_plan_sweep", "rp_plan_launch", "rp_plan_free",
            "rp_autotune_sweep", "rp_tune_set", "rp_tune_get", "rp_gram_error",
@@ -94,6 +94,10 @@ def load_library(path: str = LIB_PATH):
     lib.rp_knn_u8.argtypes = [vp, i64, i32, vp, i64, vp, i64, i32, vp, vp]
     lib.rp_knn_u8_noalloc.restype = i32
     lib.rp_knn_u8_noalloc.argtypes = [vp, i64, i32, vp, i64, vp, i64, i32, i32, vp, vp]
+    lib.rp_build_slow.restype = i32
+    lib.rp_build_slow.argtypes = [vp, i32, i64, i32, Alpha, i32, vp, vp, vp]
+    lib.rp_f32_band.restype = i32
+    lib.rp_f32_band.argtypes = [i32, C.POINTER(C.c_double)]
     lib.rp_search.restype = i32
     lib.rp_search.argtypes = [vp, vp, i64, i32, i32, vp, vp, vp, vp]
     lib.rp_read_counters.restype = i32
@@ -192,6 +196,29 @@ def knn_u8(points: torch.Tensor, K: int, query_ids: Optional[torch.Tensor] = Non
     _check(lib.rp_knn_u8(points.data_ptr(), n, d, _ptr(query_ids), nq, _ptr(cand_ids), nc,
                          int(K), out.data_ptr(), _stream_ptr(stream)))
     return out
+
+
+def build_slow(points: torch.Tensor, alpha, R: int, stream=None):
+    """The slow-preprocessing graph (rp_build_slow): RobustPrune(p, P \\ {p},
+    alpha, R) for every point; returns (nbr [n, R] int32, deg [n] int32)."""
+    lib = load_library()
+    _need_cuda(points)
+    num, den = as_alpha(alpha)
+    n, d = points.shape
+    nb = torch.empty((n, int(R)), dtype=torch.int32, device=points.device)
+    dg = torch.empty(n, dtype=torch.int32, device=points.device)
+    _check(lib.rp_build_slow(points.data_ptr(), _dtype_code(points), n, d, Alpha(num, den),
+                             int(R), nb.data_ptr(), dg.data_ptr(), _stream_ptr(stream)))
+    return nb, dg
+
+
+def f32_band(d: int) -> Tuple[float, float, float, int]:
+    """(c1, c2, c3, chunk) of the float32 kernel's rounding band at dimension
+    d and its accumulator chunk length (rp_f32_band; host only)."""
+    lib = load_library()
+    out = (C.c_double * 4)()
+    _check(lib.rp_f32_band(int(d), out))
+    return out[0], out[1], out[2], int(out[3])
 
 
 def knn_u8_noalloc(points: torch.Tensor, K: int, out: torch.Tensor,
