@@ -121,6 +121,7 @@ __device__ __forceinline__ double canon_rows(const float* __restrict__ a,
   double acc = 0.0;
   int k = 0;
   if (VEC) {
+#pragma unroll 4
     for (; k + 4 <= d; k += 4) {
       const float4 x = *(const float4*)(a + k);
       const float4 y = *(const float4*)(b + k);
@@ -139,6 +140,85 @@ __device__ __forceinline__ double canon_rows(const float* __restrict__ a,
     acc = __fma_rn(t, t, acc);
   }
   return acc;
+}
+
+// The same value computed by a whole wavefront, for one pair: the
+// differences t_k = (double)a_k - (double)b_k of up to 1,024 dimensions are
+// requested at once (coalesced) and staged in buf (LDS, >= d doubles, 16-byte
+// aligned), then every lane sums t_k^2 in order k = 0 .. d - 1 from the
+// broadcast reads, so the result is uniform and equal to canon_rows.  One
+// memory round trip per 1,024 dimensions instead of one per 4 (a lane's own
+// loop waits for each load before its fused multiply-add).
+template <bool VEC>
+__device__ __forceinline__ double canon_rows_wave(const float* __restrict__ a,
+                                                  const float* __restrict__ b, int d,
+                                                  double* buf, int lane) {
+  if (VEC) {
+    for (int k0 = 0; k0 < d; k0 += 1024) {
+      float4 va[4], vb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + 256 * u + 4 * lane;
+        if (k < d) {
+          va[u] = *(const float4*)(a + k);
+          vb[u] = *(const float4*)(b + k);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + 256 * u + 4 * lane;
+        if (k < d) {
+          *(double2*)(buf + k) =
+              make_double2((double)va[u].x - (double)vb[u].x, (double)va[u].y - (double)vb[u].y);
+          *(double2*)(buf + k + 2) =
+              make_double2((double)va[u].z - (double)vb[u].z, (double)va[u].w - (double)vb[u].w);
+        }
+      }
+    }
+  } else {
+    for (int k0 = 0; k0 < d; k0 += 512) {
+      float va[8], vb[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = k0 + 64 * u + lane;
+        if (k < d) {
+          va[u] = a[k];
+          vb[u] = b[k];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = k0 + 64 * u + lane;
+        if (k < d) buf[k] = (double)va[u] - (double)vb[u];
+      }
+    }
+  }
+  wave_sync();
+  double acc = 0.0;
+  int k = 0;
+#pragma unroll 8
+  for (; k + 2 <= d; k += 2) {
+    const double2 t = *(const double2*)(buf + k);
+    acc = __fma_rn(t.x, t.x, acc);
+    acc = __fma_rn(t.y, t.y, acc);
+  }
+  if (k < d) {
+    const double t = buf[k];
+    acc = __fma_rn(t, t, acc);
+  }
+  wave_sync();  // every read is done before buf is written again
+  return acc;
+}
+
+// Pairs of one ambiguous step that the wavefront rechecks one at a time
+// (more go lane-parallel, one pair per lane).
+constexpr int kWaveRechecks = 8;
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, l);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), l);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
 __device__ __forceinline__ bool key_less(uint64_t ah, uint32_t al, uint64_t bh, uint32_t bl) {
@@ -855,6 +935,29 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
   }
 
   // ---- a7: greedy, all alphas ---------------------------------------------------
+  // The ranks of mask am (one word; lane l holds rank l's id and S(p, .)) that
+  // row pid prunes at alpha ai, from canonical FP64 distances: a few pairs by
+  // the whole wavefront each (the x_p region of LDS is free after the pass),
+  // more one per lane.
+  auto recheck = [&](uint64_t am, int pid, int idl, double swl,
+                     int ai) __attribute__((always_inline)) -> uint64_t {
+    const float* xr = X + (int64_t)pid * d;
+    if (__popcll(am) <= kWaveRechecks) {
+      uint64_t pm = 0;
+      for (uint64_t m = am; m != 0; m &= m - 1) {
+        const int j = __builtin_ctzll(m);
+        const int idj = __builtin_amdgcn_readlane(idl, j);
+        const double sx = canon_rows_wave<VEC>(xr, X + (int64_t)idj * d, d, xq, lane);
+        if (alpha_test_f64(a.num2[ai], a.den2[ai], sx, readlane_f64(swl, j))) pm |= 1ull << j;
+      }
+      return pm;
+    }
+    bool prune = false;
+    if ((am >> lane) & 1ull)
+      prune = alpha_test_f64(a.num2[ai], a.den2[ai], canon_rows<VEC>(xr, X + (int64_t)idl * d, d),
+                             swl);
+    return __ballot(prune);
+  };
   // CAP: some output bounds R below r_max, so a chain can reach its largest R
   int rmax[NA];
 #pragma unroll
@@ -934,13 +1037,7 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
               const uint64_t am = uniform_u64(amb[ai]);
               if (am) {
                 const int pid = __builtin_amdgcn_readlane(id_rank[0], istar[ai]);
-                bool prune = false;
-                if ((am >> lane) & 1ull) {
-                  const double sx =
-                      canon_rows<VEC>(X + (int64_t)pid * d, X + (int64_t)id_rank[0] * d, d);
-                  prune = alpha_test_f64(a.num2[ai], a.den2[ai], sx, sw[0]);
-                }
-                alive[ai][0] &= ~(uint64_t)__ballot(prune);
+                alive[ai][0] &= ~recheck(am, pid, id_rank[0], sw[0], ai);
                 rechecks += __popcll(am);
               }
             }
@@ -1020,13 +1117,7 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
         for (int w = 0; w < NW; ++w) {
           const uint64_t am = uniform_u64(amb[ai][w]);
           if (am) {
-            bool prune = false;
-            if ((am >> lane) & 1ull) {
-              const double sx =
-                  canon_rows<VEC>(X + (int64_t)pid * d, X + (int64_t)id_rank[w] * d, d);
-              prune = alpha_test_f64(a.num2[ai], a.den2[ai], sx, sw[w]);
-            }
-            alive[ai][w] &= ~(uint64_t)__ballot(prune);
+            alive[ai][w] &= ~recheck(am, pid, id_rank[w], sw[w], ai);
             rechecks += __popcll(am);
           }
         }
