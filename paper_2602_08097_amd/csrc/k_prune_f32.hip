@@ -287,10 +287,17 @@ __device__ __forceinline__ void split8(const float (&x)[8], const float4& p0, co
   }
 }
 
-// C += A B^T over one 16-dimension step in three products: hi hi', hi lo', lo hi'.
+// C += A B^T over one 16-dimension step in three products: hi hi', hi lo', lo hi'
+// (FRESH: C = A B^T, the first step of an accumulator chunk).
+template <bool FRESH = false>
 __device__ __forceinline__ void gram3(v16f& c, const v8h& ah, const v8h& al, const v8h& bh,
                                       const v8h& bl) {
-  c = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, c, 0, 0, 0);
+  if constexpr (FRESH) {
+    const v16f z = {};
+    c = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, z, 0, 0, 0);
+  } else {
+    c = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, c, 0, 0, 0);
+  }
   c = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, c, 0, 0, 0);
   c = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, c, 0, 0, 0);
 }
@@ -399,8 +406,9 @@ __device__ __forceinline__ bool block_in_use(int c, int nbu) {
   return c == 0 || (c < 3 ? nbu > 1 : nbu > 2);
 }
 
-// acc += cur, then cur = 0 (a fresh accumulator for the next chunk).
-template <int NB>
+// acc += cur, then (ZERO) cur = 0 for the next chunk; without ZERO the next
+// chunk's first products start from zero instead.
+template <int NB, bool ZERO = true>
 __device__ __forceinline__ void chunk_flush(v16f (&cur)[Shape<NB>::NP], float* acc, int lane,
                                             int nbu) {
   constexpr int NP = Shape<NB>::NP;
@@ -417,8 +425,10 @@ __device__ __forceinline__ void chunk_flush(v16f (&cur)[Shape<NB>::NP], float* a
       t.w += cur[c][4 * q + 3];
       *a = t;
     }
+    if (ZERO) {
 #pragma unroll
-    for (int v = 0; v < 16; ++v) cur[c][v] = 0.f;
+      for (int v = 0; v < 16; ++v) cur[c][v] = 0.f;
+    }
   }
 }
 
@@ -463,7 +473,13 @@ __device__ __forceinline__ void gram_pass(Ring<NB>& ring, const float* const (&r
   const int nsteps = (d + 15) >> 4;
   const bool ragged = (d & 15) != 0;
   constexpr int kChunkSteps = kDC / 16;
-  auto step = [&](const Step<NB>& q, int s) {
+  // chunks of PF steps start at the first step of each round of the ring, so
+  // that step's products can start from zero (no accumulator clearing) and
+  // the last step of the round ends the chunk
+  constexpr bool kFreshStart = CSUM && kChunkSteps == PF;
+  auto step = [&](const Step<NB>& q, int s, auto pos_c) {
+    constexpr int POS = decltype(pos_c)::value;  // position in the round of the ring
+    constexpr bool F = kFreshStart && POS == 0;
     const int o0 = 16 * s + 8 * half;
     float x[NB][8];
 #pragma unroll
@@ -482,23 +498,24 @@ __device__ __forceinline__ void gram_pass(Ring<NB>& ring, const float* const (&r
     const float4 p1 = *(const float4*)(xs + o0 + 4);
     v8h hi[NB], lo[NB];
     split8(x[0], p0, p1, scf, hi[0], lo[0]);
-    gram3(cur[blk(0, 0)], hi[0], lo[0], hi[0], lo[0]);
+    gram3<F>(cur[blk(0, 0)], hi[0], lo[0], hi[0], lo[0]);
     if (nbu > 1) {
       split8(x[1], p0, p1, scf, hi[1], lo[1]);
-      gram3(cur[blk(0, 1)], hi[0], lo[0], hi[1], lo[1]);
-      gram3(cur[blk(1, 1)], hi[1], lo[1], hi[1], lo[1]);
+      gram3<F>(cur[blk(0, 1)], hi[0], lo[0], hi[1], lo[1]);
+      gram3<F>(cur[blk(1, 1)], hi[1], lo[1], hi[1], lo[1]);
     }
     if constexpr (NB > 2) {
       if (nbu > 2) {
         split8(x[2], p0, p1, scf, hi[2], lo[2]);
-        gram3(cur[blk(0, 2)], hi[0], lo[0], hi[2], lo[2]);
-        gram3(cur[blk(1, 2)], hi[1], lo[1], hi[2], lo[2]);
-        gram3(cur[blk(2, 2)], hi[2], lo[2], hi[2], lo[2]);
+        gram3<F>(cur[blk(0, 2)], hi[0], lo[0], hi[2], lo[2]);
+        gram3<F>(cur[blk(1, 2)], hi[1], lo[1], hi[2], lo[2]);
+        gram3<F>(cur[blk(2, 2)], hi[2], lo[2], hi[2], lo[2]);
       }
     }
     // a fresh accumulator every kDC dimensions
-    if (CSUM && ((s % kChunkSteps) == kChunkSteps - 1 || s == nsteps - 1))
-      chunk_flush<NB>(cur, acc, lane, nbu);
+    const bool chunk_end = kFreshStart ? POS == PF - 1 : (s % kChunkSteps) == kChunkSteps - 1;
+    if (CSUM && (chunk_end || s == nsteps - 1))
+      chunk_flush<NB, !kFreshStart>(cur, acc, lane, nbu);
     if (PROW) {
       sp[0] = row_step(sp[0], x[0], x[1], xq + 16 * s);
       if constexpr (NB > 2) {
@@ -516,22 +533,22 @@ __device__ __forceinline__ void gram_pass(Ring<NB>& ring, const float* const (&r
     {
       const Step<NB> c = qa;
       if (s + PF < nsteps) qa = fetch_step<NB, VEC>(rows, d, s + PF, half);
-      step(c, s);
+      step(c, s, std::integral_constant<int, 0>{});
     }
     if (s + 1 < nsteps) {
       const Step<NB> c = qb;
       if (s + 1 + PF < nsteps) qb = fetch_step<NB, VEC>(rows, d, s + 1 + PF, half);
-      step(c, s + 1);
+      step(c, s + 1, std::integral_constant<int, 1>{});
     }
     if (PF > 2 && s + 2 < nsteps) {
       const Step<NB> c = qc;
       if (s + 2 + PF < nsteps) qc = fetch_step<NB, VEC>(rows, d, s + 2 + PF, half);
-      step(c, s + 2);
+      step(c, s + 2, std::integral_constant<int, 2>{});
     }
     if (PF > 3 && s + 3 < nsteps) {
       const Step<NB> c = qd;
       if (s + 3 + PF < nsteps) qd = fetch_step<NB, VEC>(rows, d, s + 3 + PF, half);
-      step(c, s + 3);
+      step(c, s + 3, std::integral_constant<int, 3>{});
     }
   }
 }
@@ -553,7 +570,7 @@ __device__ __forceinline__ void store_block(float* St, const float* sr, const v1
     const int rr = 8 * (v >> 2) + (v & 3);
     const float4 nq = nrow[v >> 2];
     const float srow = (v & 3) == 0 ? nq.x : (v & 3) == 1 ? nq.y : (v & 3) == 2 ? nq.z : nq.w;
-    const float val = (srow + scol) - 2.f * acc[v];
+    const float val = __builtin_fmaf(-2.f, acc[v], srow + scol);  // 2 acc is exact
     base[32 * rr] = (BI != BJ || below > rr) ? val : __builtin_inff();
   }
 }
