@@ -230,7 +230,7 @@ def batched_kernel_name(dtype, r_max, d):
         if d % 16 == 0 and r_max <= 128 and d <= 128:
             return "prune_u8_wide_kernel"
         return "prune_plain_kernel"
-    if r_max <= 64 or (r_max <= 96 and d <= 3328):
+    if r_max <= 64 or (r_max <= 96 and d <= 3408):
         return "prune_f32_kernel"
     return "prune_plain_kernel"
 
@@ -447,7 +447,7 @@ def serve_main(args):
     import torch
 
     import workloads
-    from paper_2602_08097_amd import Graph, Server
+    from paper_2602_08097_amd import Graph, Server, knn_u8_sets
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -455,13 +455,27 @@ def serve_main(args):
     t0 = time.time()
     w = workloads.build("serve_u8", n=args.n, nq=args.nq, device=dev)
     n, d = w.X.shape
-    log(f"serve workload: n={n} d={d} ({time.time() - t0:.1f} s incl. component 128-NN)")
+    log(f"serve workload: n={n} d={d} ({time.time() - t0:.1f} s incl. the generator's "
+        f"component 128-NN)")
     X = torch.from_numpy(w.X).to(dev)
-    g_knn = Graph(X, torch.from_numpy(w.knn).to(dev), torch.from_numpy(w.knn_deg).to(dev), w.start)
+    # base lists on the GPU: rp_knn_u8 over each component's candidate set
+    torch.cuda.synchronize()
+    t0 = time.time()
+    knn = knn_u8_sets(X, w.knn.shape[1], w.components)
+    torch.cuda.synchronize()
+    knn_s = time.time() - t0
+    same = bool(np.array_equal(knn.cpu().numpy(), w.knn))
+    log(f"rp_knn_u8 over {len(w.components)} component sets: {knn_s:.2f} s, equal to the "
+        f"generator's lists: {same}")
+    g_knn = Graph(X, knn, torch.from_numpy(w.knn_deg).to(dev), w.start)
     t0 = time.time()
     nb, dg = g_knn.prune(spec.base_alpha, spec.base_R)
     torch.cuda.synchronize()
-    log(f"base graph alpha={spec.base_alpha} R={spec.base_R}: {time.time() - t0:.1f} s")
+    base_s = time.time() - t0
+    log(f"base graph alpha={spec.base_alpha} R={spec.base_R}: {base_s:.1f} s")
+    build = {"knn": "rp_knn_u8 over the component candidate sets", "knn_s": round(knn_s, 3),
+             "knn_equals_generator_lists": same, "base_prune_s": round(base_s, 3),
+             "base_prune_kernel": batched_kernel_name(np.uint8, spec.knn_k, d)}
     g_knn.free()
     start = w.start
     del w
@@ -508,7 +522,8 @@ def serve_main(args):
                                    f"R=64 over component-restricted 128-NN; Poisson mix "
                                    f"5% prune / 95% query batches, {args.requests} requests "
                                    f"per rate", "budget_bytes": budget,
-                       "plain_prune_ms": plain_ms, "batched_one_prune_ms": one_ms},
+                       "plain_prune_ms": plain_ms, "batched_one_prune_ms": one_ms,
+                       "build": build},
             "runs": runs}
     print(json.dumps(line), flush=True)
 

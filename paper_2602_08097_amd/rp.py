@@ -198,6 +198,22 @@ def knn_u8(points: torch.Tensor, K: int, query_ids: Optional[torch.Tensor] = Non
     return out
 
 
+def knn_u8_sets(points: torch.Tensor, K: int, sets, stream=None) -> torch.Tensor:
+    """Restricted exact K-NN lists with rp_knn_u8: `sets` holds (query ids,
+    candidate ids) pairs (int32 arrays or device tensors); each query's list
+    is its K nearest candidates by (S, id), itself excluded.  Returns an
+    (n, K) int32 tensor, -1 padded and -1 for points in no set."""
+    n = points.shape[0]
+    out = torch.full((n, int(K)), -1, dtype=torch.int32, device=points.device)
+    for q, c in sets:
+        q = torch.as_tensor(q, dtype=torch.int32).to(points.device)
+        c = torch.as_tensor(c, dtype=torch.int32).to(points.device)
+        if q.numel() == 0:
+            continue
+        out[q.long()] = knn_u8(points, K, query_ids=q, cand_ids=c, stream=stream)
+    return out
+
+
 def build_slow(points: torch.Tensor, alpha, R: int, stream=None):
     """The slow-preprocessing graph (rp_build_slow): RobustPrune(p, P \\ {p},
     alpha, R) for every point; returns (nbr [n, R] int32, deg [n] int32)."""

@@ -26,7 +26,7 @@ def _say(msg):
 
 @pytest.fixture(scope="module")
 def serve10m():
-    from paper_2602_08097_amd import Graph
+    from paper_2602_08097_amd import Graph, knn_u8_sets
 
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -35,7 +35,13 @@ def serve10m():
     w = workloads.build("serve_u8", nq=2_000, device=dev)
     spec = w.spec
     X = torch.from_numpy(w.X).to(dev)
-    g0 = Graph(X, torch.from_numpy(w.knn).to(dev), torch.from_numpy(w.knn_deg).to(dev), w.start)
+    # the base lists on the GPU: exact (S, id) K-NN restricted to each point's
+    # component sets (rp_knn_u8), equal to the generator's lists
+    _say("rp_knn_u8 over the component sets")
+    knn = knn_u8_sets(X, w.knn.shape[1], w.components)
+    assert np.array_equal(knn.cpu().numpy(), w.knn)
+    g0 = Graph(X, knn, torch.from_numpy(w.knn_deg).to(dev), w.start)
+    del knn
     nb, dg = g0.prune(spec.base_alpha, spec.base_R)
     torch.cuda.synchronize()
     g0.free()

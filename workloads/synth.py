@@ -84,6 +84,9 @@ class Workload:
     start: int                    # medoid
     targets: Optional[np.ndarray]  # n int32 degree targets (uneven configs)
     sample: np.ndarray            # sorted node sample (int32)
+    # component-restricted lists (knn_near > 0): per component, its members and
+    # the candidate ids of their lists (both sorted int32)
+    components: Optional[List[Tuple[np.ndarray, np.ndarray]]] = None
 
 
 def _streams(seed: int):
@@ -255,46 +258,63 @@ def _knn_torch(X: np.ndarray, K: int, device, batch: Optional[int]) -> np.ndarra
     return out.cpu().numpy()
 
 
-def knn_by_component(X: np.ndarray, labels: np.ndarray, centres: np.ndarray, K: int, near: int,
-                     device, batch: int = 2048) -> np.ndarray:
-    """n x K int32 lists: for each uint8 point, its K nearest among the points
-    of its own component and of the `near` components with the nearest centres
-    (self excluded), ascending by S, then id within the K kept (ties at the
-    K-th place may keep either id).  A labelled stand-in for exact K-NN at a
-    size where the brute force is too costly; the lists are input data."""
-    import torch
-
-    assert X.dtype == np.uint8 and X.shape[1] * 255 * 255 * 2 < (1 << 24)
-    n, d = X.shape
+def component_sets(labels: np.ndarray, centres: np.ndarray, near: int
+                   ) -> List[Tuple[np.ndarray, np.ndarray]]:
+    """Per component: its members and the candidates of their lists (the
+    members of the component and of the `near` components with the nearest
+    centres), both sorted int32."""
     comps = centres.shape[0]
     cd = ((centres[:, None, :] - centres[None, :, :]) ** 2).sum(-1)
     np.fill_diagonal(cd, np.inf)
     nearest = np.argsort(cd, axis=1, kind="stable")[:, :near]
     order = np.argsort(labels, kind="stable")
     bounds = np.concatenate([[0], np.cumsum(np.bincount(labels, minlength=comps))])
-    members = [np.sort(order[bounds[c]:bounds[c + 1]]) for c in range(comps)]
+    members = [np.sort(order[bounds[c]:bounds[c + 1]]).astype(np.int32) for c in range(comps)]
+    return [(members[c],
+             np.sort(np.concatenate([members[c]] + [members[o] for o in nearest[c]]))
+             .astype(np.int32)) for c in range(comps)]
+
+
+def knn_by_component(X: np.ndarray, labels: np.ndarray, centres: np.ndarray, K: int, near: int,
+                     device, batch: int = 2048) -> np.ndarray:
+    """n x K int32 lists: for each uint8 point, its K nearest among the points
+    of its own component and of the `near` components with the nearest centres
+    (self excluded), ascending by the key (S, id), so the lists are exact and
+    unique.  A labelled stand-in for exact K-NN at a size where the brute
+    force over all points is too costly; the lists are input data."""
+    import torch
+
+    assert X.dtype == np.uint8 and X.shape[1] * 255 * 255 * 2 < (1 << 24)
+    n, d = X.shape
+    sets = component_sets(labels, centres, near)
     Xt = torch.from_numpy(X).to(device)
     Xf = Xt.to(torch.float32)                      # every partial sum is an exact integer
     nrm = (Xt.to(torch.int64) ** 2).sum(dim=1).to(torch.float32)
     out = torch.full((n, K), -1, dtype=torch.int32, device=device)
-    for c in range(comps):
-        mem = members[c]
+    for mem, cand in sets:
         if mem.size == 0:
             continue
-        cand = np.sort(np.concatenate([mem] + [members[o] for o in nearest[c]]))
         ct = torch.from_numpy(cand).to(device)
         Xc, nc = Xf[ct], nrm[ct]
         kk = min(K, cand.size - 1)
         for a in range(0, mem.size, batch):
             q = torch.from_numpy(mem[a:a + batch]).to(device)
-            S = nrm[q][:, None] + nc[None, :] - 2.0 * (Xf[q] @ Xc.T)   # exact
+            S = nrm[q][:, None] + nc[None, :] - 2.0 * (Xf[q] @ Xc.T)   # exact integers
             S[torch.arange(q.numel(), device=device), torch.searchsorted(ct, q)] = float("inf")
             vals, idx = torch.topk(S, kk, dim=1, largest=False, sorted=True)
-            key = (vals.to(torch.int64) << 32) | ct[idx]
+            key = (vals.to(torch.int64) << 32) | ct[idx].to(torch.int64)
+            # rows with more candidates at the K-th distance than places left:
+            # take the smallest ids among the tied ones
+            sk = vals[:, kk - 1:kk]
+            for r in torch.nonzero((S <= sk).sum(dim=1) > kk).flatten().tolist():
+                cols = torch.nonzero(S[r] <= sk[r]).flatten()
+                kr = (S[r, cols].to(torch.int64) << 32) | ct[cols].to(torch.int64)
+                key[r] = torch.sort(kr).values[:kk]
             key, _ = torch.sort(key, dim=1)
             out[q, :kk] = (key & 0xFFFFFFFF).to(torch.int32)
             del S, vals, idx, key
-    torch.cuda.synchronize(device)
+    if out.is_cuda:
+        torch.cuda.synchronize(device)
     return out.cpu().numpy()
 
 
@@ -306,6 +326,7 @@ def build(name: str, n: Optional[int] = None, nq: Optional[int] = None, seed: in
     X, labels, centres = make_points_labelled(spec, n, seed)
     Q = make_queries(spec, nq, seed)
     K = knn_k or spec.knn_k
+    comp = component_sets(labels, centres, spec.knn_near) if spec.knn_near > 0 else None
     if with_knn and spec.knn_near > 0 and device is not None:
         knn = knn_by_component(X, labels, centres, min(K, X.shape[0] - 1), spec.knn_near, device)
     else:
@@ -313,7 +334,7 @@ def build(name: str, n: Optional[int] = None, nq: Optional[int] = None, seed: in
     knn_deg = None if knn is None else (knn >= 0).sum(axis=1).astype(np.int32)
     targets = degree_targets(X.shape[0], seed) if spec.uneven_degrees else None
     smp = node_sample(X.shape[0], sample or spec.sample, seed)
-    return Workload(spec, X, Q, knn, knn_deg, medoid(X), targets, smp)
+    return Workload(spec, X, Q, knn, knn_deg, medoid(X), targets, smp, comp)
 
 
 def rational_str(a: Alpha) -> str:
