@@ -86,8 +86,8 @@ typedef struct {
  * degree is outside [0, r_max] or any listed id outside [0, n), RP_EINVAL if
  * a float32 point has a NaN or infinite coordinate.  On success *out receives a new
  * handle.  The handle owns one device array per point (|x|^2 for uint8 points,
- * max_k |x_k| for float32 ones) and, for float32 graphs with r_max <= 96, one
- * byte per vertex: the scale exponent of the vertex's frame, computed from
+ * max_k |x_k| for float32 ones) and, for float32 graphs that the batched
+ * kernel serves (see rp_graph_derive), one byte per vertex: the scale exponent of the vertex's frame, computed from
  * its list here so that sweeps need not read it per candidate.
  */
 rp_status rp_load_graph(const void* points, int32_t dtype, int64_t n, int32_t d,
@@ -99,8 +99,9 @@ rp_status rp_load_graph(const void* points, int32_t dtype, int64_t n, int32_t d,
  * example a pruned graph, to search it).  Shares base's points and start
  * vertex; borrows nbr/deg like rp_load_graph and validates them the same way
  * (synchronous, as rp_load_graph), and computes its own per-vertex frame
- * exponents for float32 graphs that the batched kernel serves (r_max <= 96,
- * and r_max <= 64 above d = 3408; n bytes).  base must outlive the derived
+ * exponents for float32 graphs that the batched kernel serves (r_max <= 64;
+ * r_max <= 96 up to d = 3408; r_max <= 128 up to d = 2048 with d % 4 == 0 and
+ * 16-byte aligned points; n bytes).  base must outlive the derived
  * handle.
  */
 rp_status rp_graph_derive(rp_graph_t base, const int32_t* nbr, const int32_t* deg,
@@ -267,8 +268,8 @@ rp_status rp_tune_get(rp_graph_t g, int32_t n_a, int32_t n_R, int32_t* waves);
  *   out[3] = max |S~ - S| / E_j, where E_j is the bound the kernel proves and
  *            uses to decide which pairs to recompute in FP64 (<= 1 means
  *            every approximate decision was safe).
- * out is a host array of 4 doubles.  Float32 graphs with out-lists of at most
- * 96 ids only (uint8 distances are exact integers).  Synchronises `stream`.
+ * out is a host array of 4 doubles.  Float32 graphs that the batched kernel
+ * serves only (see rp_graph_derive; uint8 distances are exact integers).  Synchronises `stream`.
  */
 rp_status rp_gram_error(rp_graph_t g, const int32_t* nodes, int64_t n_nodes, double* out,
                         void* stream);

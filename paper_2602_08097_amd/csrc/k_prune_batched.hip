@@ -2,7 +2,7 @@
 //
 // uint8 points with out-lists of at most 64 ids run the int8-MFMA kernel
 // (k_prune_u8.hip), of 65..128 ids at d <= 128 its four-block form
-// (k_prune_u8_wide.hip); float32 points with out-lists of at most 96 ids run
+// (k_prune_u8_wide.hip); float32 points with out-lists of at most 128 ids run
 // the FP16-MFMA kernel with FP64 recheck (k_prune_f32.hip); other shapes run
 // the plain kernel once per output.
 #include <map>

@@ -399,11 +399,11 @@ __device__ __forceinline__ void ring_fill(Ring<NB>& r, const float* const (&rows
 // S~ tile takes afterwards: block c's 16 values of lane l sit at
 // acc + 1024 c + 256 q + 4 l + (v % 4) for v = 4 q + (v % 4), so every access
 // is a 16-byte vector load or store of consecutive lanes.  Each word has one
-// owner lane.  Blocks in use are (0,0); (0,1), (1,1) when two row blocks hold
-// slots; the rest with three.
+// owner lane.  Block (i, j) is in use when row block j holds listed slots
+// (nbu > j): c = blk(i, j) is below 1, 3, 6, 10 for j = 0, 1, 2, 3.
 template <int NB>
 __device__ __forceinline__ bool block_in_use(int c, int nbu) {
-  return c == 0 || (c < 3 ? nbu > 1 : nbu > 2);
+  return c == 0 || (c < 3 ? nbu > 1 : c < 6 ? nbu > 2 : nbu > 3);
 }
 
 // acc += cur, then (ZERO) cur = 0 for the next chunk; without ZERO the next
@@ -462,7 +462,8 @@ __device__ __forceinline__ void chunk_load(v16f (&cur)[Shape<NB>::NP], const flo
 // One pass over this lane's rows (rows[b]: block b's row l % 32) whose first
 // PF steps are in `ring`: the Gram blocks into cur (chunk sums into acc with
 // CSUM) and, with PROW, the canonical S(p, .) of slot lane (sp[0], rows of
-// blocks 0 and 1) and of slot 64 + l % 32 (sp[1], block 2).  nbu: blocks in use.
+// blocks 0 and 1) and of slot 64 + lane (sp[1], rows of blocks 2 and 3; with
+// three blocks lanes 32..63 repeat block 2).  nbu: blocks in use.
 template <int NB, bool CSUM, bool PROW, bool VEC, int PF>
 __device__ __forceinline__ void gram_pass(Ring<NB>& ring, const float* const (&rows)[NB], int d,
                                           int nbu, const double* __restrict__ xq,
@@ -512,6 +513,15 @@ __device__ __forceinline__ void gram_pass(Ring<NB>& ring, const float* const (&r
         gram3<F>(cur[blk(2, 2)], hi[2], lo[2], hi[2], lo[2]);
       }
     }
+    if constexpr (NB > 3) {
+      if (nbu > 3) {
+        split8(x[3], p0, p1, scf, hi[3], lo[3]);
+        gram3<F>(cur[blk(0, 3)], hi[0], lo[0], hi[3], lo[3]);
+        gram3<F>(cur[blk(1, 3)], hi[1], lo[1], hi[3], lo[3]);
+        gram3<F>(cur[blk(2, 3)], hi[2], lo[2], hi[3], lo[3]);
+        gram3<F>(cur[blk(3, 3)], hi[3], lo[3], hi[3], lo[3]);
+      }
+    }
     // a fresh accumulator every kDC dimensions
     const bool chunk_end = kFreshStart ? POS == PF - 1 : (s % kChunkSteps) == kChunkSteps - 1;
     if (CSUM && (chunk_end || s == nsteps - 1))
@@ -519,7 +529,7 @@ __device__ __forceinline__ void gram_pass(Ring<NB>& ring, const float* const (&r
     if (PROW) {
       sp[0] = row_step(sp[0], x[0], x[1], xq + 16 * s);
       if constexpr (NB > 2) {
-        if (nbu > 2) sp[1] = row_step(sp[1], x[2], x[2], xq + 16 * s);
+        if (nbu > 2) sp[1] = row_step(sp[1], x[2], x[NB > 3 ? 3 : 2], xq + 16 * s);
       }
     }
   };
@@ -595,7 +605,7 @@ __device__ __forceinline__ float row_zmin(const float* St, const float* invt, in
 // Workgroups of up to 8 wavefronts for 64 candidates, 4 for 96 (whose
 // registers take a whole SIMD lane file); one vertex per wavefront.
 template <int NA, int NB, bool CSUM, bool VEC, int PF, bool CAP, bool DIAG>
-__global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphView g, SweepArgs a, F32Args fa,
+__global__ __launch_bounds__(NB >= 3 ? 256 : 512) void prune_f32_kernel(GraphView g, SweepArgs a, F32Args fa,
                                                         DevCounters* ctr, int32_t wave_lds) {
   using SH = Shape<NB>;
   constexpr int NW = SH::NW;
@@ -646,7 +656,7 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
     constexpr int NL = sizeof(rows) / sizeof(rows[0]);
 #pragma unroll
     for (int b = 0; b < NL; ++b) {
-      const int id = b < 2 ? __shfl(ids[0], 32 * b + l32, 64) : __shfl(ids[NW - 1], l32, 64);
+      const int id = __shfl(ids[b >> 1], 32 * (b & 1) + l32, 64);
       rows[b] = X + (int64_t)(id >= 0 ? id : (int)p) * d;
     }
   };
@@ -835,11 +845,20 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
       store_block<2, 2>(St, sr, acc_of(blk(2, 2)), l32, half);
     }
   }
-  // tile entry (i, rank of word w of this lane) = St[32 i + lbase[w]]; the
+  if constexpr (NB > 3) {
+    if (nbu > 3) {
+      store_block<0, 3>(St, sr, acc_of(blk(0, 3)), l32, half);
+      store_block<1, 3>(St, sr, acc_of(blk(1, 3)), l32, half);
+      store_block<2, 3>(St, sr, acc_of(blk(2, 3)), l32, half);
+      store_block<3, 3>(St, sr, acc_of(blk(3, 3)), l32, half);
+    }
+  }
+  // tile entry (i, rank of word w of this lane) = St[32 i + lbase[w]] for the
+  // rows i the column block holds (i < 32 (cb + 1)); with three blocks the
   // second word's lanes 32..63 (ranks past 95, never alive) read in bounds
   int lbase[NW];
   lbase[0] = l32 + 1024 * half;
-  if (NW == 2) lbase[NW - 1] = cb_base(2) + l32;
+  if (NW == 2) lbase[NW - 1] = (NB > 3 && half ? cb_base(3) : cb_base(2)) + l32;
 
   if constexpr (DIAG) {
     wave_sync();
@@ -926,7 +945,8 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
     }
     wave_sync();
     float zmin[NW];
-    // rank lane: column blocks 0 (rows 0..31 only), 1 and 2; entries on and
+    // row = rank lane: column blocks 0 (rows 0..31 only), 1, 2 and 3; row =
+    // rank 64 + lane: column block 2 (rows 64..95 only) and 3; entries on and
     // below the diagonal hold +inf
     zmin[0] = __builtin_inff();
     if (lane < 32) zmin[0] = row_zmin(St, invt, 0, lane, zmin[0]);
@@ -936,6 +956,12 @@ __global__ __launch_bounds__(NB == 3 ? 256 : 512) void prune_f32_kernel(GraphVie
       if (nbu > 2) {
         zmin[0] = row_zmin(St, invt, 2, lane, zmin[0]);
         if (lane < 32) zmin[1] = row_zmin(St, invt, 2, 64 + lane, zmin[1]);
+      }
+      if constexpr (NB > 3) {
+        if (nbu > 3) {
+          zmin[0] = row_zmin(St, invt, 3, lane, zmin[0]);
+          zmin[1] = row_zmin(St, invt, 3, 64 + lane, zmin[1]);
+        }
       }
     }
     float eps = 0.f;
@@ -1272,15 +1298,18 @@ struct Plan {
 
 Plan plan_of(const GraphView& g) {
   Plan pl;
-  pl.nb = g.r_max > 64 ? 3 : 2;
+  pl.nb = g.r_max > 96 ? 4 : g.r_max > 64 ? 3 : 2;
   pl.csum = g.d > 128;
   pl.vec = (g.d % 4) == 0 && (((uintptr_t)g.X) & 15) == 0;
-  pl.wave_lds = pl.nb == 3 ? wave_lds_bytes<3>(g.d) : wave_lds_bytes<2>(g.d);
+  pl.wave_lds = pl.nb == 4   ? wave_lds_bytes<4>(g.d)
+                 : pl.nb == 3 ? wave_lds_bytes<3>(g.d)
+                              : wave_lds_bytes<2>(g.d);
   return pl;
 }
 
 // Steps in flight: two for 64 candidates (three wavefronts per SIMD fit),
-// four for 96 (one wavefront per SIMD).
+// four for 96 (one wavefront per SIMD), two for 128 (whose ten accumulator
+// blocks take most of a wavefront's registers).
 template <int NB>
 constexpr int prefetch_steps() {
   return NB == 3 ? 4 : 2;
@@ -1292,12 +1321,12 @@ hipError_t launch_shape(const GraphView& g, const SweepArgs& a, const F32Args& f
   constexpr int PF = prefetch_steps<NB>();
   const int waves =
       min(waves_for(TuneKey{kKernelF32, g.dtype, g.d, g.r_max, a.n_alpha, a.n_out}, wave_lds),
-          NB == 3 ? 4 : 8);  // within the launch bounds
+          NB >= 3 ? 4 : 8);  // within the launch bounds
   const dim3 grid((unsigned)((g.n + waves - 1) / waves)), block(64 * waves);
   const size_t shmem = (size_t)wave_lds * waves;
   // a bound below r_max needs the chains' keep counts (always kept for the
   // rarer shapes: 96 candidates, unaligned rows)
-  bool cap = NB == 3 || !VEC;
+  bool cap = NB >= 3 || !VEC;
   for (int o = 0; o < a.n_out; ++o) cap = cap || a.out[o].R < g.r_max;
 #define RP_LAUNCH_F32(NA_)                                                                 \
   case NA_:                                                                                \
@@ -1339,6 +1368,10 @@ hipError_t launch_diag(const GraphView& g, const SweepArgs& a, const F32Args& fa
 template <template <int, bool, bool> class L>
 hipError_t dispatch(const Plan& pl, const GraphView& g, const SweepArgs& a, const F32Args& fa,
                     DevCounters* ctr, hipStream_t s) {
+  if (pl.nb == 4) {  // 16-byte row slices only (prune_f32_shape_ok)
+    return pl.csum ? L<4, true, true>::run(g, a, fa, ctr, s, pl.wave_lds)
+                   : L<4, false, true>::run(g, a, fa, ctr, s, pl.wave_lds);
+  }
   if (pl.nb == 3) {
     if (pl.csum)
       return pl.vec ? L<3, true, true>::run(g, a, fa, ctr, s, pl.wave_lds)
@@ -1423,11 +1456,15 @@ void f32_band(int d, double* c) {
   c[3] = csum ? kDC : d;
 }
 
-// Lists of at most 96 ids whose LDS fits a workgroup (96 candidates above
-// d = 3408 do not: those graphs take the plain kernel).
+// Lists of at most 128 ids whose LDS fits a workgroup (96 candidates above
+// d = 3408 and 128 above d = 2048 do not: those graphs take the plain
+// kernel); lists of 97..128 ids need 16-byte row slices.
 bool prune_f32_shape_ok(const GraphView& g) {
-  return g.dtype == RP_F32 && g.r_max <= 96 && g.d <= kMaxDimF32 && g.n <= (1ll << 25) &&
-         g.maxabs != nullptr && plan_of(g).wave_lds <= kMaxLdsPerGroup;
+  if (g.dtype != RP_F32 || g.r_max > 128 || g.d > kMaxDimF32 || g.n > (1ll << 25) ||
+      g.maxabs == nullptr)
+    return false;
+  const Plan pl = plan_of(g);
+  return pl.wave_lds <= kMaxLdsPerGroup && (pl.nb < 4 || pl.vec);
 }
 
 bool prune_f32_supported(const GraphView& g) {

@@ -115,7 +115,7 @@ rp_status add_maxabs(rp_graph* g, hipStream_t s) {
   return RP_OK;
 }
 
-// Float32 graphs that the batched prune serves (lists of at most 96 ids) get
+// Float32 graphs that the batched prune serves (lists of at most 128 ids) get
 // the frame exponent of every vertex once, so a sweep reads one byte per
 // vertex instead of max|x| of every candidate.
 rp_status add_frame_exponents(rp_graph* g, hipStream_t stream) {
@@ -382,7 +382,7 @@ rp_status rp_gram_error(rp_graph_t g, const int32_t* nodes, int64_t n_nodes, dou
   if (!out) return fail(RP_EINVAL, "out is null");
   const rp::GraphView& v = g->view;
   if (v.dtype != RP_F32 || !rp::prune_f32_supported(v))
-    return fail(RP_EINVAL, "needs a float32 graph with out-lists of at most 96 ids");
+    return fail(RP_EINVAL, "needs a float32 graph that the batched kernel serves");
   if (n_nodes < 0 || n_nodes >= (1ll << 31)) return fail(RP_EINVAL, "bad n_nodes");
   for (int i = 0; i < 4; ++i) out[i] = 0.0;
   if (n_nodes == 0) return ok();

@@ -302,12 +302,13 @@ def test_u8_thresholds_at_exact_boundaries():
         assert np.array_equal(_np(dg), e_deg), a
 
 
-@pytest.mark.parametrize("r_max", [64, 96])
+@pytest.mark.parametrize("r_max", [64, 96, 128])
 @pytest.mark.parametrize("d", [5, 32, 100, 300])
 def test_edge_cases_f32_batched_kernel(d, r_max):
-    """float32 shapes that take the split-FP16 MFMA kernel (up to 64 and up to
-    96 candidates, d with and without a ragged 32-wide chunk, rows that are
-    not 16-byte multiples): exact ties (values on a 1/4 grid make many alpha
+    """float32 shapes that take the split-FP16 MFMA kernel (up to 64, 96 and
+    128 candidates (two, three and four row blocks; 128 with 16-byte rows,
+    else the plain kernel), d with and without a ragged 32-wide chunk, rows
+    that are not 16-byte multiples): exact ties (values on a 1/4 grid make many alpha
     tests land exactly on the threshold and go to the FP64 recheck), duplicate
     points, ragged and empty lists, wide dynamic range."""
     rng = np.random.default_rng(d + r_max)
@@ -324,7 +325,7 @@ def test_edge_cases_f32_batched_kernel(d, r_max):
     deg[2:6] = r_max
     g = _graph(X, nbr, deg, 0)
     alphas = [(1, 1), (21, 20), (6, 5), (3, 2), (2, 1)]
-    Rs = [64, 7]
+    Rs = [64, 7] + ([r_max] if r_max > 64 else [])
     g.counters(reset=True)
     outs = g.prune_sweep(alphas, Rs)
     for o, (nb, dg) in enumerate(outs):
