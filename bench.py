@@ -472,7 +472,7 @@ def serve_main(args):
     nb, dg = g_knn.prune(spec.base_alpha, spec.base_R)
     torch.cuda.synchronize()
     base_s = time.time() - t0
-    log(f"base graph alpha={spec.base_alpha} R={spec.base_R}: {base_s:.1f} s")
+    log(f"base graph alpha={spec.base_alpha} R={spec.base_R}: {base_s * 1e3:.1f} ms")
     build = {"knn": "rp_knn_u8 over the component candidate sets", "knn_s": round(knn_s, 3),
              "knn_equals_generator_lists": same, "base_prune_s": round(base_s, 3),
              "base_prune_kernel": batched_kernel_name(np.uint8, spec.knn_k, d)}
