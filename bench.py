@@ -357,13 +357,33 @@ def cpu_baseline(w, spec, budget_s, sample=20_000):
     finally:
         os.sched_setaffinity(0, set(allowed))
     outs = len(spec.sweep) * len(spec.Rs)
+    search = None
+    if n <= 20_000:
+        # GreedySearch on the oracle's own full base graph (built here, not
+        # timed), pinned like the prune loop, over up to 1,000 queries
+        o_nbr, o_deg, _ = oracle.prune_graph(w.X, w.knn, w.knn_deg, *spec.base_alpha,
+                                             spec.base_R, threads=8)
+        if w.targets is not None:
+            o_deg = np.minimum(o_deg, w.targets)
+        Qs = w.Q[:1000]
+        os.sched_setaffinity(0, {core})
+        try:
+            t1 = time.perf_counter()
+            oracle.search(w.X, o_nbr, o_deg, w.start, Qs, spec.k, spec.Ls[0])
+            st = time.perf_counter() - t1
+        finally:
+            os.sched_setaffinity(0, set(allowed))
+        search = {"qps": Qs.shape[0] / st, "queries": int(Qs.shape[0]), "k": spec.k,
+                  "L": spec.Ls[0], "graph": "the oracle's base graph", "cores": 1}
     rec = {"value": done / dt, "unit": "nodes/s", "cores": 1, "kind": "oracle",
            "sample": f"{done} sampled vertices x {len(spec.sweep)} alphas x {len(spec.Rs)} R "
                      f"(base rows from the oracle's own RobustPrune of the K-NN lists), "
                      f"{dt:.1f} s on one core",
            "node_prunes_per_s": done * outs / dt,
            "pairs_per_node_prune": pairs / max(1, done * outs),
-           "pinned_core": core}
+           "pinned_core": core,
+           "search": search if search is not None else
+           "not timed at this size (the oracle's full base graph is too costly to build here)"}
     rec.update(host_facts())
     return rec
 
@@ -793,8 +813,10 @@ def run_config(name, args, dev, headline):
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(w, spec, args.cpu_budget if headline else
                                            args.cpu_budget / 3)
+        cs = rec["cpu_baseline"]["search"]
         log(f"cpu oracle: {rec['cpu_baseline']['value']:.1f} nodes/s "
-            f"({rec['cpu_baseline']['sample']})")
+            f"({rec['cpu_baseline']['sample']})"
+            + (f"; search {cs['qps']:.1f} QPS on one core" if isinstance(cs, dict) else ""))
     g.free()
     g_knn.free()
     del X, knn, base_nbr, base_deg, outs
