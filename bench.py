@@ -230,7 +230,8 @@ def batched_kernel_name(dtype, r_max, d):
         if d % 16 == 0 and r_max <= 128 and d <= 128:
             return "prune_u8_wide_kernel"
         return "prune_plain_kernel"
-    if r_max <= 64 or (r_max <= 96 and d <= 3408) or (r_max <= 128 and d <= 2048 and d % 4 == 0):
+    # gfx950 gives a workgroup 160 KiB of LDS: every d up to 4096 fits
+    if r_max <= 96 or (r_max <= 128 and d % 4 == 0):
         return "prune_f32_kernel"
     return "prune_plain_kernel"
 

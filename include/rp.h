@@ -99,9 +99,9 @@ rp_status rp_load_graph(const void* points, int32_t dtype, int64_t n, int32_t d,
  * example a pruned graph, to search it).  Shares base's points and start
  * vertex; borrows nbr/deg like rp_load_graph and validates them the same way
  * (synchronous, as rp_load_graph), and computes its own per-vertex frame
- * exponents for float32 graphs that the batched kernel serves (r_max <= 64;
- * r_max <= 96 up to d = 3408; r_max <= 128 up to d = 2048 with d % 4 == 0 and
- * 16-byte aligned points; n bytes).  base must outlive the derived
+ * exponents for float32 graphs that the batched kernel serves (r_max <= 128,
+ * 97..128 only with d % 4 == 0 and 16-byte aligned points, and one vertex's
+ * LDS within the device's LDS per workgroup: every d on gfx950; n bytes).  base must outlive the derived
  * handle.
  */
 rp_status rp_graph_derive(rp_graph_t base, const int32_t* nbr, const int32_t* deg,
@@ -240,8 +240,8 @@ void rp_plan_free(rp_plan_t p); /* NULL is ignored */
 
 /*
  * Launch tuning.  The batched kernels run one vertex per wavefront and pack
- * `waves` vertices into each workgroup (1, 2, 4 or 8, within 64 KiB of LDS
- * per workgroup).  rp_autotune_sweep times the sweep of these arguments for
+ * `waves` vertices into each workgroup (1, 2, 4 or 8, within the device's
+ * LDS per workgroup, 160 KiB on gfx950).  rp_autotune_sweep times the sweep of these arguments for
  * every candidate (one warm-up and three timed launches each, HIP events on
  * `stream`), keeps the fastest for this graph shape (dtype, d, r_max) and
  * sweep shape (n_a, n_R) for the rest of the process, and returns it in

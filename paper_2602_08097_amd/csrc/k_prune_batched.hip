@@ -34,6 +34,31 @@ void set_tuned_waves(const TuneKey& k, int waves) {
   else g_tune[key_of(k)] = waves;
 }
 
+namespace {
+constexpr int kLdsDevices = 64;
+std::mutex g_lds_mu;
+int g_lds[kLdsDevices];  // 0 = not queried yet
+}  // namespace
+
+int max_lds_per_group() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kLdsDevices) {
+    (void)hipGetLastError();
+    return 65536;
+  }
+  std::lock_guard<std::mutex> lk(g_lds_mu);
+  if (g_lds[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        v < 65536) {
+      (void)hipGetLastError();
+      v = 65536;
+    }
+    g_lds[dev] = v;
+  }
+  return g_lds[dev];
+}
+
 bool prune_u8_supported(const GraphView& g);
 hipError_t launch_prune_u8(const GraphView& g, const SweepArgs& a, DevCounters* ctr,
                            hipStream_t s);

@@ -1456,15 +1456,16 @@ void f32_band(int d, double* c) {
   c[3] = csum ? kDC : d;
 }
 
-// Lists of at most 128 ids whose LDS fits a workgroup (96 candidates above
-// d = 3408 and 128 above d = 2048 do not: those graphs take the plain
-// kernel); lists of 97..128 ids need 16-byte row slices.
+// Lists of at most 128 ids whose LDS fits a workgroup of the device (on
+// gfx950, 160 KiB: every d up to 4096; with 64 KiB, 96 candidates up to
+// d = 3408 and 128 up to d = 2048); lists of 97..128 ids need 16-byte row
+// slices.  Other graphs take the plain kernel.
 bool prune_f32_shape_ok(const GraphView& g) {
   if (g.dtype != RP_F32 || g.r_max > 128 || g.d > kMaxDimF32 || g.n > (1ll << 25) ||
       g.maxabs == nullptr)
     return false;
   const Plan pl = plan_of(g);
-  return pl.wave_lds <= kMaxLdsPerGroup && (pl.nb < 4 || pl.vec);
+  return pl.wave_lds <= max_lds_per_group() && (pl.nb < 4 || pl.vec);
 }
 
 bool prune_f32_supported(const GraphView& g) {

@@ -458,7 +458,7 @@ rp_status rp_autotune_sweep(rp_graph_t g, const rp_alpha* alphas, int32_t n_a, c
   hipError_t err = hipSuccess;
   for (int c = 0; c < 4 && err == hipSuccess; ++c) {
     const int w = kCand[c];
-    if ((size_t)w * rp::batched_wave_lds(v) > (size_t)rp::kMaxLdsPerGroup) continue;
+    if ((size_t)w * rp::batched_wave_lds(v) > (size_t)rp::max_lds_per_group()) continue;
     rp::set_tuned_waves(key, w);
     float t[3];
     err = rp::launch_prune_batched(v, a, g->ctr, s);  // warm-up

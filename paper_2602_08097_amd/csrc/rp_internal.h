@@ -135,7 +135,9 @@ inline double f32_rel_bound(int d) {
 constexpr int kKernelU8 = 1;
 constexpr int kKernelF32 = 2;
 constexpr int kKernelU8Wide = 3;
-constexpr int kMaxLdsPerGroup = 65536;
+// LDS one workgroup may take on the current device (163,840 bytes on
+// gfx950; 65,536 if the runtime cannot tell), queried once per device.
+int max_lds_per_group();
 struct TuneKey {
   int32_t kernel, dtype, d, r_max, n_alpha, n_out;
 };
@@ -148,7 +150,7 @@ int batched_wave_lds(const GraphView& g);    // LDS bytes per wavefront of that 
 inline int waves_for(const TuneKey& k, int wave_lds) {
   int w = tuned_waves(k);
   if (w < 1) w = 1;
-  while (w > 1 && (size_t)w * wave_lds > (size_t)kMaxLdsPerGroup) w >>= 1;
+  while (w > 1 && (size_t)w * wave_lds > (size_t)max_lds_per_group()) w >>= 1;
   return w;
 }
 

@@ -158,17 +158,24 @@ def test_f32_coordinates_near_1e35():
     g.free()
 
 
-def test_f32_ninety_six_candidates_beyond_batched_lds():
-    """96 candidates at d = 4000 exceed the batched kernel's LDS per workgroup:
-    the sweep takes the plain kernel and still equals the oracle."""
-    rng = np.random.default_rng(4000)
-    n, d = 110, 4000
+@pytest.mark.parametrize("r_max,d", [(96, 4000), (128, 3000)])
+def test_f32_long_rows_beyond_64_kib_of_lds(r_max, d):
+    """One vertex of 96 candidates at d = 4000 (72 KiB) or of 128 at d = 3000
+    (76 KiB) needs more than 64 KiB of LDS: on gfx950 (160 KiB per workgroup)
+    the batched kernel takes it, elsewhere the plain kernel; either way the
+    sweep equals the oracle, and the measured error stays in the band."""
+    rng = np.random.default_rng(d + r_max)
+    n = 140
     X = rng.standard_normal((n, d)).astype(np.float32)
-    nbr, deg = _random_lists(rng, n, 96)
+    nbr, deg = _random_lists(rng, n, r_max)
     g = _graph(X, nbr, deg)
     alphas = [(1, 1), (6, 5)]
-    outs = g.prune_sweep(alphas, [96, 20])
-    _check(X, nbr, deg, outs, alphas, [96, 20], False)
+    outs = g.prune_sweep(alphas, [r_max, 20])
+    _check(X, nbr, deg, outs, alphas, [r_max, 20], False)
+    props = torch.cuda.get_device_properties(0)
+    if getattr(props, "shared_memory_per_block", 0) >= 160 * 1024:
+        err = g.gram_error(torch.arange(0, n, dtype=torch.int32, device=_dev()))
+        assert err["pairs"] > 0 and err["max_err_over_bound"] <= 1.0
     g.free()
 
 
