@@ -31,28 +31,33 @@ def serve10m():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     dev = torch.device("cuda:0")
-    _say("building serve_u8 (10M x 128)")
-    w = workloads.build("serve_u8", nq=2_000, device=dev)
+    _say("generating serve_u8 (10M x 128)")
+    w = workloads.build("serve_u8", nq=2_000, device=dev, with_knn=False)
     spec = w.spec
+    K = spec.knn_k
+    nodes = w.sample[:2000]
+    # the generator's lists (input data) on the sampled rows only: the oracle's
+    # base rows need no others
+    _say("generator lists of the sampled rows")
+    ref = workloads.synth.knn_on_sets(w.X, w.components, K, dev, rows=nodes)
+    ref_deg = (ref >= 0).sum(axis=1).astype(np.int32)
     X = torch.from_numpy(w.X).to(dev)
     # the base lists on the GPU: exact (S, id) K-NN restricted to each point's
-    # component sets (rp_knn_u8), equal to the generator's lists
+    # component sets (rp_knn_u8), equal to the generator's on the sample
     _say("rp_knn_u8 over the component sets")
-    knn = knn_u8_sets(X, w.knn.shape[1], w.components)
-    assert np.array_equal(knn.cpu().numpy(), w.knn)
-    g0 = Graph(X, knn, torch.from_numpy(w.knn_deg).to(dev), w.start)
-    del knn
+    knn = knn_u8_sets(X, K, w.components)
+    kdeg = (knn >= 0).sum(dim=1, dtype=torch.int32)
+    assert np.array_equal(knn.cpu().numpy()[nodes], ref[nodes])
+    g0 = Graph(X, knn, kdeg, w.start)
     nb, dg = g0.prune(spec.base_alpha, spec.base_R)
     torch.cuda.synchronize()
     g0.free()
+    del knn, kdeg
     base = Graph(X, nb, dg, w.start)
-    nodes = w.sample[:2000]
     _say("oracle base rows on the sample")
-    o_nbr, o_deg, _ = oracle.prune_graph(w.X, w.knn, w.knn_deg, *spec.base_alpha, spec.base_R,
+    o_nbr, o_deg, _ = oracle.prune_graph(w.X, ref, ref_deg, *spec.base_alpha, spec.base_R,
                                          nodes=nodes, threads=THREADS)
-    knn = w.knn
-    w.knn = None  # 5 GB of lists: the oracle needs only the sampled rows from here on
-    del knn
+    del ref
     return w, base, nodes, o_nbr, o_deg
 
 

@@ -282,11 +282,20 @@ def knn_by_component(X: np.ndarray, labels: np.ndarray, centres: np.ndarray, K: 
     (self excluded), ascending by the key (S, id), so the lists are exact and
     unique.  A labelled stand-in for exact K-NN at a size where the brute
     force over all points is too costly; the lists are input data."""
+    return knn_on_sets(X, component_sets(labels, centres, near), K, device, batch=batch)
+
+
+def knn_on_sets(X: np.ndarray, sets, K: int, device, rows: Optional[np.ndarray] = None,
+                batch: int = 2048) -> np.ndarray:
+    """n x K int32 lists over (members, candidates) sets as knn_by_component
+    builds them; with `rows`, only those points' lists are computed (the rest
+    stay -1)."""
     import torch
 
     assert X.dtype == np.uint8 and X.shape[1] * 255 * 255 * 2 < (1 << 24)
     n, d = X.shape
-    sets = component_sets(labels, centres, near)
+    if rows is not None:
+        sets = [(np.intersect1d(mem, rows).astype(np.int32), cand) for mem, cand in sets]
     Xt = torch.from_numpy(X).to(device)
     Xf = Xt.to(torch.float32)                      # every partial sum is an exact integer
     nrm = (Xt.to(torch.int64) ** 2).sum(dim=1).to(torch.float32)
