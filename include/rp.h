@@ -282,8 +282,10 @@ rp_status rp_gram_error(rp_graph_t g, const int32_t* nodes, int64_t n_nodes, dou
  * is measured against rebuilding it at the new alpha.  O(n^2) work per point.
  *   out_nbr: n x R int32, row p the kept ids in the order Algorithm 1 adds
  *            them (ascending (S(p, .), id)), -1 padded; out_deg: n int32.
- * Distances and the alpha test as everywhere in this header.  A workspace of
- * at most 1 GiB is allocated and freed in stream order on `stream`.
+ * Distances and the alpha test as everywhere in this header.  Coordinates
+ * are not checked here: a NaN or infinity gives unspecified lists (the call
+ * still ends).  A workspace of at most 1 GiB is allocated and freed in stream
+ * order on `stream`; the call returns once the work is enqueued.
  */
 rp_status rp_build_slow(const void* points, int32_t dtype, int64_t n, int32_t d, rp_alpha alpha,
                         int32_t R, int32_t* out_nbr, int32_t* out_deg, void* stream);
