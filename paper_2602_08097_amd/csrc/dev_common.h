@@ -15,6 +15,9 @@ __device__ __forceinline__ double canon_sq_f32(const float* __restrict__ a,
   double acc = 0.0;
   int k = 0;
   if ((((uintptr_t)a | (uintptr_t)b) & 15) == 0 && (d & 3) == 0) {
+    // unrolled so that several 16-byte loads are in flight before the
+    // multiply-add chain consumes them (one round trip per 32 dimensions)
+#pragma unroll 8
     for (; k < d; k += 4) {
       const float4 x = *(const float4*)(a + k);
       const float4 y = *(const float4*)(b + k);
@@ -53,6 +56,7 @@ __device__ __forceinline__ float sq_f32(const float* __restrict__ a,
   float acc = 0.f;
   int k = 0;
   if ((((uintptr_t)a | (uintptr_t)b) & 15) == 0 && (d & 3) == 0) {
+#pragma unroll 8
     for (; k < d; k += 4) {
       const float4 x = *(const float4*)(a + k);
       const float4 y = *(const float4*)(b + k);

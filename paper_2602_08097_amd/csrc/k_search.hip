@@ -46,6 +46,7 @@ __device__ __forceinline__ uint32_t sq_u8_q(const uint8_t* __restrict__ qs,
   uint32_t dot = 0;
   int k = 0;
   if (((d & 15) | ((uintptr_t)x & 15)) == 0)  // 16-byte aligned rows
+#pragma unroll 8
   for (; k + 16 <= d; k += 16) {
     const uint4 a = *(const uint4*)(qs + k);
     const uint4 b = *(const uint4*)(x + k);
