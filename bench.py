@@ -942,8 +942,8 @@ def main():
                           int(t[2]) if t else None)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 (sharding "
+                                   "the sweep over GPUs is designed but not built)"}))
         sys.exit(2)
     if args.serve:
         serve_main(args)
